@@ -1,0 +1,137 @@
+/*
+ * bgemm -- batched FP64 GEMM for AMD Instinct MI355X (CDNA4, gfx950).
+ *
+ * The operation is the paper's Eq. 1 (Section II): for i = 1..N,
+ *     C_i <- alpha * op(A_i) * op(B_i) + beta * C_i
+ * over a very large batch of small, independent instances, real FP64.
+ * op(X) = X for transX = 'N'/'n' and X^T for 'T'/'t'/'C'/'c' (real data, so
+ * the conjugate transpose is the transpose).  op(A_i) is m x k, op(B_i) is
+ * k x n, C_i is m x n.
+ *
+ * Layout.  Every matrix is column-major: element (r, c) of a matrix with
+ * leading dimension ld is at offset r + c * ld (doubles).  A with 'N' is
+ * stored m x k (lda >= max(1, m)); with 'T' it is stored k x m
+ * (lda >= max(1, k)).  B with 'N' is stored k x n (ldb >= max(1, k)); with 'T'
+ * n x k (ldb >= max(1, n)).  ldc >= max(1, m).  Rows r >= rows of a column
+ * (the ld padding) are never read or written.
+ *
+ * Memory and ownership.  Matrices, the pointer arrays dA/dB/dC (one device
+ * pointer per instance), the per-instance size arrays of the variable-size
+ * call and d_info are DEVICE memory owned by the caller; the library never
+ * frees or retains them.  alpha and beta are host values.  The handle owns
+ * only its workspace, allocated by bg_create / bg_set_workspace; no compute
+ * entry point allocates.
+ *
+ * Semantics of the scalars (reference BLAS; the paper is silent):
+ *   beta == 0            C is not read (NaN in C does not propagate);
+ *   alpha == 0 or k == 0 A and B are not read; C <- beta * C, exactly 0 when
+ *                        beta == 0, untouched (bit-identical) when beta == 1;
+ *   m == 0 or n == 0     nothing happens.
+ *
+ * Aliasing.  C_i may not overlap any C_j (j != i), A_j or B_j.  A_i and B_i
+ * may alias each other (Gram products).  Results do not depend on the order
+ * of the instances in the pointer arrays or on what else is in the batch:
+ * each instance's summation order is fixed by its own sizes.
+ *
+ * Synchronisation.  Calls are asynchronous on the handle's stream: SUCCESS
+ * means the work was enqueued.  A device fault surfaces as BG_STATUS_DEVICE_ERROR
+ * from a later call or from the caller's stream synchronisation.
+ *
+ * Threads.  A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef BGEMM_H
+#define BGEMM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BG_STATUS_SUCCESS = 0,
+  BG_STATUS_INVALID_VALUE = 1,   /* an argument breaks the rules below */
+  BG_STATUS_NOT_SUPPORTED = 2,   /* valid but outside this build (e.g. sizes beyond int32 grids) */
+  BG_STATUS_DEVICE_ERROR = 3,    /* a HIP call failed */
+  BG_STATUS_ALLOC_FAILED = 4,    /* workspace allocation failed */
+  BG_STATUS_INVALID_HANDLE = 5,  /* NULL or destroyed handle */
+  BG_STATUS_WORKSPACE_TOO_SMALL = 6 /* variable-size batch larger than the workspace plans for */
+} bg_status_t;
+
+typedef struct bg_handle* bg_handle_t;
+
+/* Library version as 10000 * major + 100 * minor + patch. */
+int bg_version(void);
+
+/* Static string naming a status code. */
+const char* bg_status_string(bg_status_t s);
+
+/* Creates a handle bound to the current HIP device, with the default stream
+ * and a workspace of BG_DEFAULT_WORKSPACE_BYTES (the environment variable
+ * BG_WORKSPACE_MB overrides the size).  *h is set only on success. */
+#define BG_DEFAULT_WORKSPACE_BYTES (64u << 20)
+bg_status_t bg_create(bg_handle_t* h);
+
+/* Frees the handle's workspace.  Work already enqueued must have finished
+ * (the call synchronises the handle's stream first). */
+bg_status_t bg_destroy(bg_handle_t h);
+
+/* Sets the stream (a hipStream_t; NULL = the default stream) that later
+ * calls enqueue on. */
+bg_status_t bg_set_stream(bg_handle_t h, void* stream);
+bg_status_t bg_get_stream(bg_handle_t h, void** stream);
+
+/* Replaces the workspace with one of `bytes` bytes (synchronises the stream).
+ * The variable-size call needs about 8 * (batch + 1) + 8 * batch / 256 bytes of
+ * planning space plus, for its fastest schedule, 4 bytes per C tile. */
+bg_status_t bg_set_workspace(bg_handle_t h, unsigned long long bytes);
+unsigned long long bg_workspace_bytes_needed(int batch);
+
+/* Argument number (reference-BLAS DGEMM numbering: 1 transa, 2 transb, 3 m,
+ * 4 n, 5 k, 7 A, 8 lda, 9 B, 10 ldb, 12 C, 13 ldc, 14 batch) of the first
+ * invalid argument of the handle's last call, 0 if that call was valid. */
+int bg_last_invalid_arg(bg_handle_t h);
+
+/* Host-only check of a uniform batched call's arguments, in the order above;
+ * touches no device.  Returns 0 when valid, else the argument number. */
+int bg_check_batched_args(char transa, char transb, int m, int n, int k,
+                          const void* dA, int lda, const void* dB, int ldb,
+                          const void* dC, int ldc, int batch);
+
+/* Uniform sizes (the paper's fixed-size batch, Section II): every instance is
+ * m x n x k with the same leading dimensions.  Quick returns, with no launch:
+ * batch == 0, m == 0, n == 0, and (alpha == 0 or k == 0) with beta == 1.
+ * Returns BG_STATUS_INVALID_VALUE (and records the argument number) for
+ * a bad trans character, m/n/k < 0, lda/ldb/ldc below their minimum,
+ * batch < 0, or a NULL pointer array when batch > 0 and the array is read. */
+bg_status_t bg_dgemm_batched(bg_handle_t h, char transa, char transb,
+                             int m, int n, int k, double alpha,
+                             const double* const* dA, int lda,
+                             const double* const* dB, int ldb, double beta,
+                             double* const* dC, int ldc, int batch);
+
+/* Variable sizes (the paper's variable-size batch, Section II): instance i
+ * has sizes d_m[i], d_n[i], d_k[i] and leading dimensions d_lda[i], d_ldb[i],
+ * d_ldc[i] (all device int arrays of length batch).  The sizes are checked on
+ * the device: an instance that breaks the rules gets d_info[i] = -(argument
+ * number: 3 m, 4 n, 5 k, 8 lda, 10 ldb, 13 ldc) and its C is left untouched;
+ * a valid one gets d_info[i] = 0.  d_info may be NULL.  All instances go into
+ * one persistent launch that pops C tiles from a device-side queue; planning
+ * is done on the device, so the host never reads the sizes.  Host-side
+ * errors: a bad trans character, batch < 0, NULL arrays when batch > 0, or
+ * BG_STATUS_WORKSPACE_TOO_SMALL. */
+bg_status_t bg_dgemm_vbatched(bg_handle_t h, char transa, char transb,
+                              const int* d_m, const int* d_n, const int* d_k,
+                              double alpha,
+                              const double* const* dA, const int* d_lda,
+                              const double* const* dB, const int* d_ldb,
+                              double beta,
+                              double* const* dC, const int* d_ldc,
+                              int batch, int* d_info);
+
+/* Overrides the size class chosen for uniform batches (-1 = automatic;
+ * 0 = 32x32 tiles, 1 = 64x64, 2 = 128x128).  For tuning and tests. */
+bg_status_t bg_set_uniform_class(bg_handle_t h, int cls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BGEMM_H */

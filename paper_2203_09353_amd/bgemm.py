@@ -1,0 +1,209 @@
+"""Python binding of the bgemm C ABI (include/bgemm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libbgemm.so``.  Torch is used for device memory and the current
+stream.  If the library is missing, importing works but every call raises
+``RuntimeError``; there is no fallback path.
+
+Matrix convention: a batch of column-major matrices (rows x cols, leading
+dimension ld) is a CUDA float64 tensor of shape (batch, cols, ld), or a list
+of (cols, ld) tensors; element (r, c) of instance b is ``t[b, c, r]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbgemm.so")
+_lib = None
+
+STATUS = {0: "SUCCESS", 1: "INVALID_VALUE", 2: "NOT_SUPPORTED", 3: "DEVICE_ERROR",
+          4: "ALLOC_FAILED", 5: "INVALID_HANDLE", 6: "WORKSPACE_TOO_SMALL"}
+
+# every symbol include/bgemm.h declares
+EXPORTS = ["bg_version", "bg_status_string", "bg_create", "bg_destroy", "bg_set_stream",
+           "bg_get_stream", "bg_set_workspace", "bg_workspace_bytes_needed",
+           "bg_last_invalid_arg", "bg_check_batched_args", "bg_dgemm_batched",
+           "bg_dgemm_vbatched", "bg_set_uniform_class"]
+
+
+class BgemmError(RuntimeError):
+    def __init__(self, fn, status, arg=0):
+        self.status = status
+        self.arg = arg
+        msg = "%s: %s" % (fn, STATUS.get(status, str(status)))
+        if arg:
+            msg += " (argument %d)" % arg
+        super().__init__(msg)
+
+
+def lib():
+    """Loads libbgemm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libbgemm.so not built: run python -m paper_2203_09353_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, c = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_char
+    L.bg_version.restype = i
+    L.bg_version.argtypes = []
+    L.bg_status_string.restype = ctypes.c_char_p
+    L.bg_status_string.argtypes = [i]
+    L.bg_create.restype = i
+    L.bg_create.argtypes = [ctypes.POINTER(vp)]
+    L.bg_destroy.restype = i
+    L.bg_destroy.argtypes = [vp]
+    L.bg_set_stream.restype = i
+    L.bg_set_stream.argtypes = [vp, vp]
+    L.bg_get_stream.restype = i
+    L.bg_get_stream.argtypes = [vp, ctypes.POINTER(vp)]
+    L.bg_set_workspace.restype = i
+    L.bg_set_workspace.argtypes = [vp, ctypes.c_ulonglong]
+    L.bg_workspace_bytes_needed.restype = ctypes.c_ulonglong
+    L.bg_workspace_bytes_needed.argtypes = [i]
+    L.bg_last_invalid_arg.restype = i
+    L.bg_last_invalid_arg.argtypes = [vp]
+    L.bg_check_batched_args.restype = i
+    L.bg_check_batched_args.argtypes = [c, c, i, i, i, vp, i, vp, i, vp, i, i]
+    L.bg_dgemm_batched.restype = i
+    L.bg_dgemm_batched.argtypes = [vp, c, c, i, i, i, d, vp, i, vp, i, d, vp, i, i]
+    L.bg_dgemm_vbatched.restype = i
+    L.bg_dgemm_vbatched.argtypes = [vp, c, c, vp, vp, vp, d, vp, vp, vp, vp, d, vp, vp, i, vp]
+    L.bg_set_uniform_class.restype = i
+    L.bg_set_uniform_class.argtypes = [vp, i]
+    _lib = L
+    return L
+
+
+def _ch(t):
+    return t.encode()[:1] if t else b"\0"
+
+
+def check_batched_args(transa, transb, m, n, k, A, lda, B, ldb, C, ldc, batch) -> int:
+    """Host-only argument check (no device); 0 or the bad argument's number."""
+    return lib().bg_check_batched_args(_ch(transa), _ch(transb), m, n, k, A, lda, B, ldb, C,
+                                       ldc, batch)
+
+
+def pointer_array(x) -> torch.Tensor:
+    """Device int64 tensor of per-instance data pointers for a (batch, cols,
+    ld) tensor or a list of tensors (kept alive by the caller)."""
+    if isinstance(x, torch.Tensor):
+        assert x.dim() == 3 and x.dtype == torch.float64 and x.is_cuda
+        nb = x.shape[0]
+        base = x.data_ptr()
+        step = x.stride(0) * 8
+        return torch.arange(nb, dtype=torch.int64, device=x.device) * step + base
+    ptrs = [t.data_ptr() for t in x]
+    dev = x[0].device if len(x) else torch.device("cuda")
+    return torch.tensor(ptrs, dtype=torch.int64, device=dev)
+
+
+class Handle:
+    """A bgemm handle on the current device, enqueuing on torch's current
+    stream at each call."""
+
+    def __init__(self, workspace_bytes: int | None = None):
+        self._L = lib()
+        h = ctypes.c_void_p()
+        st = self._L.bg_create(ctypes.byref(h))
+        if st != 0:
+            raise BgemmError("bg_create", st)
+        self._h = h
+        if workspace_bytes:
+            self.set_workspace(workspace_bytes)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.bg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        self._L.bg_set_stream(self._h, torch.cuda.current_stream().cuda_stream)
+
+    def set_workspace(self, nbytes: int):
+        st = self._L.bg_set_workspace(self._h, int(nbytes))
+        if st != 0:
+            raise BgemmError("bg_set_workspace", st)
+
+    def set_uniform_class(self, cls: int):
+        st = self._L.bg_set_uniform_class(self._h, int(cls))
+        if st != 0:
+            raise BgemmError("bg_set_uniform_class", st)
+
+    def last_invalid_arg(self) -> int:
+        return self._L.bg_last_invalid_arg(self._h)
+
+    # raw entry points: pointer arrays and sizes as given --------------------
+    def dgemm_batched_raw(self, transa, transb, m, n, k, alpha, pA, lda, pB, ldb, beta, pC, ldc,
+                          batch) -> int:
+        self._sync_stream()
+        return self._L.bg_dgemm_batched(self._h, _ch(transa), _ch(transb), m, n, k, float(alpha),
+                                        pA, lda, pB, ldb, float(beta), pC, ldc, batch)
+
+    def dgemm_vbatched_raw(self, transa, transb, pm, pn, pk, alpha, pA, plda, pB, pldb, beta, pC,
+                           pldc, batch, pinfo) -> int:
+        self._sync_stream()
+        return self._L.bg_dgemm_vbatched(self._h, _ch(transa), _ch(transb), pm, pn, pk,
+                                         float(alpha), pA, plda, pB, pldb, float(beta), pC, pldc,
+                                         batch, pinfo)
+
+    # tensor-level helpers ------------------------------------------------------
+    def batched(self, A, B, C, m, n, k, alpha=1.0, beta=0.0, transa="N", transb="N",
+                ptrs=None):
+        """C <- alpha op(A) op(B) + beta C for stacked (batch, cols, ld) CUDA
+        tensors or lists of (cols, ld) tensors; the leading dimensions are read
+        from the last axis.  ``ptrs`` may pass precomputed (pA, pB, pC)
+        pointer tensors.  Returns the pointer tensors."""
+        a0, b0, c0 = A[0], B[0], C[0]
+        lda, ldb, ldc = a0.shape[-1], b0.shape[-1], c0.shape[-1]
+        batch = C.shape[0] if isinstance(C, torch.Tensor) else len(C)
+        if ptrs is None:
+            ptrs = (pointer_array(A), pointer_array(B), pointer_array(C))
+        pA, pB, pC = ptrs
+        st = self.dgemm_batched_raw(transa, transb, m, n, k, alpha, pA.data_ptr(), lda,
+                                    pB.data_ptr(), ldb, beta, pC.data_ptr(), ldc, batch)
+        if st != 0:
+            raise BgemmError("bg_dgemm_batched", st, self.last_invalid_arg())
+        return ptrs
+
+    def vbatched(self, As, Bs, Cs, ms, ns, ks, alpha=1.0, beta=0.0, transa="N", transb="N",
+                 ldas=None, ldbs=None, ldcs=None, info=None, ptrs=None):
+        """Variable sizes; As, Bs, Cs are lists of (cols, ld) CUDA tensors (or
+        ``ptrs`` = (pA, pB, pC) device pointer tensors).  ms, ns, ks (and the
+        ld arrays) are CUDA int32 tensors or sequences.  Returns the device
+        info tensor (int32)."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def ivec(x):
+            if isinstance(x, torch.Tensor):
+                return x.to(device=dev, dtype=torch.int32).contiguous()
+            return torch.tensor(list(x), dtype=torch.int32, device=dev)
+
+        batch = len(ms)
+        ldas = ivec([a.shape[-1] for a in As] if ldas is None else ldas)
+        ldbs = ivec([b.shape[-1] for b in Bs] if ldbs is None else ldbs)
+        ldcs = ivec([c.shape[-1] for c in Cs] if ldcs is None else ldcs)
+        ms, ns, ks = ivec(ms), ivec(ns), ivec(ks)
+        if info is None:
+            info = torch.empty(batch, dtype=torch.int32, device=dev)
+        if ptrs is None:
+            ptrs = (pointer_array(As), pointer_array(Bs), pointer_array(Cs))
+        pA, pB, pC = ptrs
+        st = self.dgemm_vbatched_raw(transa, transb, ms.data_ptr(), ns.data_ptr(), ks.data_ptr(),
+                                     alpha, pA.data_ptr(), ldas.data_ptr(), pB.data_ptr(),
+                                     ldbs.data_ptr(), beta, pC.data_ptr(), ldcs.data_ptr(),
+                                     batch, info.data_ptr())
+        if st != 0:
+            raise BgemmError("bg_dgemm_vbatched", st, self.last_invalid_arg())
+        return info

@@ -1,0 +1,70 @@
+// Internal declarations shared by the C-ABI layer (bgemm_api.cpp) and the
+// kernel launchers (bgemm_kernels.hip).  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bg {
+
+// Tile shapes.  A "size class" is one tile configuration of the MFMA tile
+// kernel: C tile BM x BN per workgroup, contraction step BK per LDS stage,
+// each wave computing a WM x WN sub-tile with 16x16x4 FP64 MFMAs.
+enum TileClass : int {
+  TC_32 = 0,     // 32x32 tile, one wave           (tiny matrices)
+  TC_64 = 1,     // 64x64 tile, four 32x32 waves   (small matrices)
+  TC_128 = 2,    // 128x128 tile, four 64x64 waves (large matrices)
+  TC_COUNT = 3
+};
+
+struct TileShape { int bm, bn, bk, threads; };
+TileShape tile_shape(TileClass c);
+
+// Picks the tile class for a uniform batch; `force` >= 0 overrides.
+TileClass pick_uniform_class(int m, int n, int k, int force);
+
+struct UniformArgs {
+  bool ta, tb;
+  int m, n, k;
+  double alpha, beta;
+  const double* const* A; int64_t lda;
+  const double* const* B; int64_t ldb;
+  double* const* C; int64_t ldc;
+  int batch;
+};
+
+// Launches the uniform batched GEMM (product path; alpha != 0, k > 0).
+hipError_t launch_uniform(const UniformArgs& a, TileClass cls, hipStream_t s);
+
+// Launches C_i <- beta * C_i (beta != 1) for every instance, used when the
+// product term vanishes (alpha == 0 or k == 0).
+hipError_t launch_scale(double beta, double* const* C, int64_t ldc, int m, int n, int batch,
+                        hipStream_t s);
+
+struct VbatchedArgs {
+  bool ta, tb;
+  const int *m, *n, *k;
+  double alpha, beta;
+  const double* const* A; const int* lda;
+  const double* const* B; const int* ldb;
+  double* const* C; const int* ldc;
+  int batch;
+  int* info;  // nullable
+};
+
+// Workspace layout used by the vbatched planner and executor.
+struct VbWorkspace {
+  void* base;
+  size_t bytes;
+};
+
+// Bytes of workspace the planner needs for `batch` instances, excluding the
+// optional tile map (which uses whatever remains).
+size_t vbatched_workspace_bytes(int batch);
+
+// Plans (validate, count tiles, prefix sums, tile map) and executes the
+// variable-size batch with a persistent kernel; all on stream `s`.
+hipError_t launch_vbatched(const VbatchedArgs& a, const VbWorkspace& ws, int num_cus,
+                           hipStream_t s);
+
+}  // namespace bg

@@ -1,0 +1,177 @@
+// Measurement kernels for the roofline denominators and the MFMA lane-layout
+// check: attainable FP64 matrix-core and vector throughput, HBM copy/read
+// bandwidth, and one FP64 MFMA on caller-supplied fragments.  Built into its
+// own library (libbgemm_microbench.so); the GEMM library does not use it.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// One v_mfma_f64_16x16x4_f64 by one wave: a[64], b[64] are the per-lane
+// source values, c[4*64] the per-lane accumulator (register v of lane l at
+// c[4*l + v]), d[4*64] receives the result in the same arrangement.
+__global__ void k_mfma_once(const double* a, const double* b, const double* c, double* d) {
+  const int l = threadIdx.x;
+  d4 acc = {c[4 * l], c[4 * l + 1], c[4 * l + 2], c[4 * l + 3]};
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[l], b[l], acc, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) d[4 * l + v] = acc[v];
+}
+
+// CHAINS independent accumulators per wave, `iters` rounds of CHAINS MFMAs.
+template <int CHAINS>
+__global__ __launch_bounds__(256) void k_mfma_peak(double* sink, int iters, double seed) {
+  const double a = seed + threadIdx.x * 1e-9, b = seed - threadIdx.x * 1e-9;
+  d4 acc[CHAINS];
+  for (int c = 0; c < CHAINS; ++c) acc[c] = d4{0.0, 0.0, 0.0, (double)c};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < CHAINS; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+  }
+  double s = 0.0;
+  for (int c = 0; c < CHAINS; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  if (s == 1234.5678) sink[threadIdx.x] = s;  // never true in practice; keeps the work
+}
+
+// FP64 vector FMA throughput: 8 independent chains per lane.
+__global__ __launch_bounds__(256) void k_valu_peak(double* sink, int iters, double seed) {
+  double x[8];
+  const double m = 1.0 + 1e-12, c = 1e-13;
+  for (int i = 0; i < 8; ++i) x[i] = seed + i + threadIdx.x;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = __builtin_fma(x[i], m, c);
+  }
+  double s = 0.0;
+  for (int i = 0; i < 8; ++i) s += x[i];
+  if (s == 1234.5678) sink[threadIdx.x] = s;
+}
+
+// Half the waves issue MFMA, half issue vector FMA: do the two share the
+// FP64 pipeline?
+__global__ __launch_bounds__(256) void k_mixed_peak(double* sink, int iters, double seed) {
+  const int wave = threadIdx.x >> 6;
+  double s = 0.0;
+  if (wave & 1) {
+    double x[8];
+    const double m = 1.0 + 1e-12, c = 1e-13;
+    for (int i = 0; i < 8; ++i) x[i] = seed + i + threadIdx.x;
+    // 8 FMAs of 128 flop per wave-instruction vs 4 MFMAs of 2048 flop: scale
+    // the loop so both halves take about the same time at equal peaks.
+    for (int it = 0; it < iters * 8; ++it) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[i] = __builtin_fma(x[i], m, c);
+    }
+    for (int i = 0; i < 8; ++i) s += x[i];
+  } else {
+    const double a = seed + threadIdx.x * 1e-9, b = seed - threadIdx.x * 1e-9;
+    d4 acc[4];
+    for (int c = 0; c < 4; ++c) acc[c] = d4{0.0, 0.0, 0.0, (double)c};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+    }
+    for (int c = 0; c < 4; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  }
+  if (s == 1234.5678) sink[threadIdx.x] = s;
+}
+
+// Streaming copy, four 16-byte loads in flight per lane per step.  n2 must be
+// a multiple of 4 * gridDim.x * blockDim.x (the host rounds it down).
+__global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                              int64_t n2) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i + 3 * stride < n2; i += 4 * stride) {
+    const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a; dst[i + stride] = b; dst[i + 2 * stride] = c; dst[i + 3 * stride] = d;
+  }
+}
+
+// Streaming read with a reduction so the loads are kept.
+__global__ __launch_bounds__(256) void k_read(const double2* __restrict__ src, int64_t n2, double* sink) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i + 3 * stride < n2; i += 4 * stride) {
+    const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    s += a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y;
+  }
+  if (s == 1234.5678) sink[threadIdx.x] = s;
+}
+
+// 4x4x4 FP64 MFMA (four 4x4 blocks, 512 flop per instruction), 8 chains.
+__global__ __launch_bounds__(256) void k_mfma4_peak(double* sink, int iters, double seed) {
+  const double a = seed + threadIdx.x * 1e-9, b = seed - threadIdx.x * 1e-9;
+  double acc[8];
+  for (int c = 0; c < 8; ++c) acc[c] = (double)c;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, acc[c], 0, 0, 0);
+  }
+  double s = 0.0;
+  for (int c = 0; c < 8; ++c) s += acc[c];
+  if (s == 1234.5678) sink[threadIdx.x] = s;
+}
+
+static float time_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
+extern "C" {
+
+int mb_mfma_f64_16x16x4(const double* a, const double* b, const double* c, double* d) {
+  hipLaunchKernelGGL(k_mfma_once, dim3(1), dim3(64), 0, 0, a, b, c, d);
+  return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
+}
+
+// kind: 0 = MFMA f64 (4 chains), 1 = vector FMA f64, 2 = mixed halves,
+//       3 = MFMA f64 with 8 chains, 4 = 4x4x4 MFMA f64 with 8 chains.
+// Returns the elapsed milliseconds of `reps` launches (negative on error).
+double mb_fp64_peak_ms(int kind, int grid, int iters, int reps, double* sink) {
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  auto launch = [&]() {
+    if (kind == 0) hipLaunchKernelGGL(k_mfma_peak<4>, dim3(grid), dim3(256), 0, 0, sink, iters, 0.5);
+    else if (kind == 1) hipLaunchKernelGGL(k_valu_peak, dim3(grid), dim3(256), 0, 0, sink, iters, 0.5);
+    else if (kind == 2) hipLaunchKernelGGL(k_mixed_peak, dim3(grid), dim3(256), 0, 0, sink, iters, 0.5);
+    else if (kind == 3) hipLaunchKernelGGL(k_mfma_peak<8>, dim3(grid), dim3(256), 0, 0, sink, iters, 0.5);
+    else hipLaunchKernelGGL(k_mfma4_peak, dim3(grid), dim3(256), 0, 0, sink, iters, 0.5);
+  };
+  launch();
+  hipEventRecord(e0, 0);
+  for (int r = 0; r < reps; ++r) launch();
+  hipEventRecord(e1, 0);
+  hipError_t err = hipEventSynchronize(e1);
+  double ms = err == hipSuccess ? (double)time_ms(e0, e1) : -1.0;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return ms;
+}
+
+// kind: 0 = copy (src -> dst, `bytes` each), 1 = read-only.
+double mb_stream_ms(int kind, const void* src, void* dst, long long bytes, int grid, int reps,
+                    double* sink) {
+  const int64_t quad = 4ll * grid * 256;
+  const int64_t n2 = (bytes / 16) / quad * quad;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  auto launch = [&]() {
+    if (kind == 0)
+      hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, 0, (const double2*)src, (double2*)dst, n2);
+    else
+      hipLaunchKernelGGL(k_read, dim3(grid), dim3(256), 0, 0, (const double2*)src, n2, sink);
+  };
+  launch();
+  hipEventRecord(e0, 0);
+  for (int r = 0; r < reps; ++r) launch();
+  hipEventRecord(e1, 0);
+  hipError_t err = hipEventSynchronize(e1);
+  double ms = err == hipSuccess ? (double)time_ms(e0, e1) : -1.0;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return ms;
+}
+
+}  // extern "C"

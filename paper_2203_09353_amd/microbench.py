@@ -1,0 +1,98 @@
+"""Binding of libbgemm_microbench.so: attainable FP64 matrix/vector peaks,
+HBM stream bandwidth and a single FP64 MFMA on given fragments.
+
+    python -m paper_2203_09353_amd.microbench      # prints a JSON summary
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbgemm_microbench.so")
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libbgemm_microbench.so not built")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.mb_mfma_f64_16x16x4.restype = ctypes.c_int
+        L.mb_mfma_f64_16x16x4.argtypes = [vp, vp, vp, vp]
+        L.mb_fp64_peak_ms.restype = ctypes.c_double
+        L.mb_fp64_peak_ms.argtypes = [ctypes.c_int] * 4 + [vp]
+        L.mb_stream_ms.restype = ctypes.c_double
+        L.mb_stream_ms.argtypes = [ctypes.c_int, vp, vp, ctypes.c_longlong, ctypes.c_int,
+                                   ctypes.c_int, vp]
+        _lib = L
+    return _lib
+
+
+def mfma_once(a, b, c):
+    """a, b: 64 per-lane values; c: (64, 4) per-lane accumulators.  Returns
+    the (64, 4) result of one v_mfma_f64_16x16x4_f64 (CPU float64 tensor)."""
+    dev = torch.device("cuda")
+    a = torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
+    b = torch.as_tensor(b, dtype=torch.float64).to(dev).contiguous()
+    c = torch.as_tensor(c, dtype=torch.float64).to(dev).contiguous()
+    d = torch.empty(64, 4, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    assert lib().mb_mfma_f64_16x16x4(a.data_ptr(), b.data_ptr(), c.data_ptr(), d.data_ptr()) == 0
+    return d.cpu()
+
+
+def fp64_peak_tflops(kind: str, grid: int | None = None, iters: int = 4000, reps: int = 5):
+    """kind: 'mfma' (4 chains), 'mfma8' (8 chains), 'valu', 'mixed'."""
+    code = {"mfma": 0, "valu": 1, "mixed": 2, "mfma8": 3, "mfma4x4": 4}[kind]
+    props = torch.cuda.get_device_properties(0)
+    grid = grid or props.multi_processor_count * 8
+    sink = torch.zeros(256, dtype=torch.float64, device="cuda")
+    ms = lib().mb_fp64_peak_ms(code, grid, iters, reps, sink.data_ptr())
+    waves = grid * 4
+    if code in (0, 3):
+        chains = 4 if code == 0 else 8
+        flop = waves * iters * chains * 2048.0
+    elif code == 4:
+        flop = waves * iters * 8 * 512.0
+    elif code == 1:
+        flop = waves * iters * 8 * 64 * 2.0
+    else:
+        half = waves / 2
+        flop = half * iters * 4 * 2048.0 + half * iters * 8 * 8 * 64 * 2.0
+    return flop * reps / (ms * 1e-3) / 1e12, ms
+
+
+def stream_gbps(kind: str, nbytes: int = 4 << 30, grid: int | None = None, reps: int = 10):
+    """kind: 'copy' (reports read + write bytes) or 'read'."""
+    props = torch.cuda.get_device_properties(0)
+    grid = grid or props.multi_processor_count * 16
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src) if kind == "copy" else src
+    sink = torch.zeros(256, dtype=torch.float64, device="cuda")
+    ms = lib().mb_stream_ms(0 if kind == "copy" else 1, src.data_ptr(), dst.data_ptr(), nbytes,
+                            grid, reps, sink.data_ptr())
+    quad = 4 * grid * 256 * 16
+    nbytes = nbytes // quad * quad
+    moved = nbytes * (2 if kind == "copy" else 1) * reps
+    del src, dst
+    return moved / (ms * 1e-3) / 1e9, ms
+
+
+def summary():
+    out = {"device": torch.cuda.get_device_name(0),
+           "cus": torch.cuda.get_device_properties(0).multi_processor_count}
+    for k in ("mfma", "mfma8", "mfma4x4", "valu", "mixed"):
+        out["fp64_%s_tflops" % k] = round(fp64_peak_tflops(k)[0], 2)
+    for k in ("copy", "read"):
+        out["hbm_%s_gbps" % k] = round(stream_gbps(k)[0], 1)
+    return out
+
+
+if __name__ == "__main__":
+    print(json.dumps(summary()))
