@@ -17,6 +17,14 @@ __global__ void k_mfma_once(const double* a, const double* b, const double* c, d
   for (int v = 0; v < 4; ++v) d[4 * l + v] = acc[v];
 }
 
+// One v_mfma_f64_4x4x4_4b_f64 (four 4x4x4 blocks) by one wave with the A
+// broadcast controls CBSZ / ABID; a, b, c, d: one value per lane.
+template <int CBSZ, int ABID>
+__global__ void k_mfma4_once(const double* a, const double* b, const double* c, double* d) {
+  const int l = threadIdx.x;
+  d[l] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[l], b[l], c[l], CBSZ, ABID, 0);
+}
+
 // CHAINS independent accumulators per wave, `iters` rounds of CHAINS MFMAs.
 template <int CHAINS>
 __global__ __launch_bounds__(256) void k_mfma_peak(double* sink, int iters, double seed) {
@@ -121,6 +129,21 @@ extern "C" {
 
 int mb_mfma_f64_16x16x4(const double* a, const double* b, const double* c, double* d) {
   hipLaunchKernelGGL(k_mfma_once, dim3(1), dim3(64), 0, 0, a, b, c, d);
+  return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
+}
+
+// mode selects (CBSZ, ABID): 0 (0,0), 1 (1,0), 2 (1,1), 3 (2,0), 4 (2,1),
+// 5 (2,3), 6 (3,0).
+int mb_mfma_f64_4x4x4(const double* a, const double* b, const double* c, double* d, int mode) {
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((k_mfma4_once<0, 0>), dim3(1), dim3(64), 0, 0, a, b, c, d); break;
+    case 1: hipLaunchKernelGGL((k_mfma4_once<1, 0>), dim3(1), dim3(64), 0, 0, a, b, c, d); break;
+    case 2: hipLaunchKernelGGL((k_mfma4_once<1, 1>), dim3(1), dim3(64), 0, 0, a, b, c, d); break;
+    case 3: hipLaunchKernelGGL((k_mfma4_once<2, 0>), dim3(1), dim3(64), 0, 0, a, b, c, d); break;
+    case 4: hipLaunchKernelGGL((k_mfma4_once<2, 1>), dim3(1), dim3(64), 0, 0, a, b, c, d); break;
+    case 5: hipLaunchKernelGGL((k_mfma4_once<2, 3>), dim3(1), dim3(64), 0, 0, a, b, c, d); break;
+    default: hipLaunchKernelGGL((k_mfma4_once<3, 0>), dim3(1), dim3(64), 0, 0, a, b, c, d); break;
+  }
   return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
 }
 

@@ -25,6 +25,8 @@ def lib():
         vp = ctypes.c_void_p
         L.mb_mfma_f64_16x16x4.restype = ctypes.c_int
         L.mb_mfma_f64_16x16x4.argtypes = [vp, vp, vp, vp]
+        L.mb_mfma_f64_4x4x4.restype = ctypes.c_int
+        L.mb_mfma_f64_4x4x4.argtypes = [vp, vp, vp, vp, ctypes.c_int]
         L.mb_fp64_peak_ms.restype = ctypes.c_double
         L.mb_fp64_peak_ms.argtypes = [ctypes.c_int] * 4 + [vp]
         L.mb_stream_ms.restype = ctypes.c_double
@@ -44,6 +46,18 @@ def mfma_once(a, b, c):
     d = torch.empty(64, 4, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     assert lib().mb_mfma_f64_16x16x4(a.data_ptr(), b.data_ptr(), c.data_ptr(), d.data_ptr()) == 0
+    return d.cpu()
+
+
+def mfma4_once(a, b, c, mode=0):
+    """One v_mfma_f64_4x4x4_4b_f64 with broadcast mode (see microbench.hip);
+    a, b, c: 64 per-lane values.  Returns the 64 results."""
+    dev = torch.device("cuda")
+    t = [torch.as_tensor(x, dtype=torch.float64).to(dev).contiguous() for x in (a, b, c)]
+    d = torch.empty(64, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    assert lib().mb_mfma_f64_4x4x4(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(),
+                                   d.data_ptr(), int(mode)) == 0
     return d.cpu()
 
 
