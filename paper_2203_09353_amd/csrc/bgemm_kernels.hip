@@ -3,69 +3,101 @@
 // Operation (the paper, Section II, Eq. 1): for every instance i,
 //   C_i <- alpha * op(A_i) * op(B_i) + beta * C_i,   column-major, FP64.
 // The paper builds each product from a 2-D grid of C tiles, one thread block
-// per tile (Section II); here one workgroup computes one C tile with the
-// 16x16x4 FP64 matrix-core instruction, operands staged through LDS.
+// per tile (Section II); here one workgroup computes one C tile on the FP64
+// matrix cores, operands staged through LDS.
 //
-// MFMA operand convention.  v_mfma_f64_16x16x4_f64 multiplies a 16x4 "A"
-// fragment by a 4x16 "B" fragment.  Lane l holds element (l % 16, l / 16) of
-// the A fragment and element (l / 16, l % 16) of the B fragment; result
-// register v (v = 0..3) of lane l holds element (l / 16 + 4 v, l % 16) of the
-// 16x16 result (checked on the device by the lane-layout test).  We feed
-// op(B)^T as the instruction's A and op(A)^T as its B, so the result block is
-// the transpose of a C block: lane l holds C(row = l % 16, col = l/16 + 4 v),
-// i.e. 16 lanes cover 16 consecutive rows of one column -- the contiguous
-// direction of column-major C, so epilogue loads/stores coalesce.
+// Matrix-core instruction.  v_mfma_f64_4x4x4_4b_f64 performs four independent
+// 4x4x4 products per wave (blocks b = 0..3).  Lane 16 s + 4 b + i holds
+// element (i, s) of block b's first operand, lane 16 s + 4 b + j holds element
+// (s, j) of its second operand, and the result element (i, j) of block b lands
+// in lane 16 i + 4 b + j (checked on the device by the lane-layout test).  On
+// gfx950 this instruction sustains about 1.5x the FP64 rate of the 16x16x4
+// form, so the tiles are built from it.
 //
-// Contraction-index permutation.  Within a 16-wide slice of k, MFMA number t
-// (t = 0..3) uses k = kk + 4*g + t in lane group g = l / 16.  Any bijection of
-// k is valid as long as both operands use it; this one lets a lane read four
-// consecutive k values of a K-contiguous operand with one 32-byte LDS read.
+// Roles.  Of the two operands of the product, one -- "P" -- is read as a
+// 16-row slab: lane 16 s + r holds P(p0 + r, k_s), so the four blocks cover
+// 16 consecutive P indices.  The other -- "Q" -- is read replicated: lane
+// 16 s + 4 b + j holds Q(q0 + j, k_s) for every b.  One instruction then
+// yields a 16 x 4 block of P x Q^T: lane 16 i + 4 b + j holds the sum over s
+// of P(p0 + 4 b + i, k_s) Q(q0 + j, k_s).  With P = op(A) and Q = op(B)^T the
+// block is a piece of C whose 16 rows sit in 16 lanes (coalesced column
+// segments); with P = op(B)^T and Q = op(A) it is a piece of C^T.  The larger
+// tiles use the second form because it needs less LDS padding.
+//
+// Contraction order.  A 16-wide slice of k starting at kk is consumed by four
+// instructions t = 0..3; instruction t gives lane group s the index
+// k = kk + 2 s + 8 (t / 2) + (t % 2).  Any bijection is valid if both operands
+// use it; this one puts each t-pair on adjacent k, so a K-contiguous operand
+// feeds two instructions with one 16-byte LDS read.  Every tile class walks k
+// in the same slices and order, so a given element of C gets the same bits
+// from every class, alone or in any batch.
 #include "bgemm_internal.h"
 
 namespace bg {
 
 typedef double d2 __attribute__((ext_vector_type(2)));
-typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Explicit address spaces: matrices are global memory (address space 1),
+// operand tiles are LDS (address space 3).  Without them the compiler falls
+// back to flat instructions, which count against both the vector-memory and
+// the LDS wait counters and so serialise LDS reads behind global prefetches.
+#define AS_GLOBAL __attribute__((address_space(1)))
+#define AS_LDS __attribute__((address_space(3)))
+typedef const AS_GLOBAL double* gcptr;
+typedef AS_GLOBAL double* gptr;
+typedef AS_LDS double* lptr;
+typedef const AS_LDS double* lcptr;
 
 // ---------------------------------------------------------------------------
-// Tile configurations
+// Tile configurations: C tile BM x BN per workgroup, BK of k per LDS stage,
+// wave tile WM x WN, SWAP selects the C^T form (P = op(B)^T, Q = op(A)).
 // ---------------------------------------------------------------------------
-template <int BM_, int BN_, int BK_, int WM_, int WN_>
+template <int BM_, int BN_, int BK_, int WM_, int WN_, bool SWAP_>
 struct Cfg {
   static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+  static constexpr bool SWAP = SWAP_;
   static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN;
   static constexpr int NT = WAVES_M * WAVES_N * 64;
-  static constexpr int FM = WM / 16, FN = WN / 16;
-  static_assert(BM % WM == 0 && BN % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "tile");
+  static constexpr int WP = SWAP ? WN : WM;   // wave extent along P
+  static constexpr int WQ = SWAP ? WM : WN;   // wave extent along Q
+  static constexpr int FP = WP / 16;          // 16-wide P slabs per wave
+  static constexpr int GQ = WQ / 4;           // 4-wide Q groups per wave
+  static_assert(BM % WM == 0 && BN % WN == 0 && WP % 16 == 0 && WQ % 4 == 0, "tile");
   static_assert(BK % 16 == 0, "BK must be a multiple of 16");
 };
 
-using Cfg32 = Cfg<32, 32, 32, 32, 32>;
-using Cfg64 = Cfg<64, 64, 32, 32, 32>;
-using Cfg128 = Cfg<128, 128, 16, 64, 64>;
+using Cfg32 = Cfg<32, 32, 32, 32, 32, false>;
+using Cfg64 = Cfg<64, 64, 32, 64, 16, false>;
+using Cfg128 = Cfg<128, 128, 16, 32, 64, true>;
 
 // ---------------------------------------------------------------------------
-// Operand tiles.  An operand tile spans BMN values of its product dimension
-// (m for A, n for B) and BK values of k.  In memory the operand is either
+// Operand tiles in LDS.  An operand tile spans BMN values of its product
+// dimension (m for A, n for B) and BK values of k.  In memory the operand is
 // MN-contiguous (A with 'N', B with 'T') or K-contiguous (A with 'T', B with
-// 'N'); LDS keeps the memory orientation with a padded stride S (doubles):
-//   MN-contiguous: lds[k * S + mn], S = BMN + 4  (S = 4 mod 8: the four lane
-//                  groups of a fragment read land in distinct bank halves)
-//   K-contiguous : lds[mn * S + k], S = BK + 2   (S = 2 mod 4: sixteen
-//                  16-byte reads of one quarter-wave hit distinct banks)
+// 'N'); LDS keeps that orientation with a padded stride S (doubles), chosen
+// per role so that one read instruction hits distinct banks (64 banks of
+// 4 bytes):
+//   P, MN-contiguous lds[k*S + mn]: S = BMN + 8  (4 S = 32 mod 64: lane
+//      groups s = 0, 1 fall in opposite bank halves)
+//   P, K-contiguous  lds[mn*S + k]: S = BK + 2   (2 S = 4 mod 8: sixteen
+//      16-byte reads of a quarter-wave are disjoint)
+//   Q, MN-contiguous lds[k*S + mn]: S = BMN + 2  (4 S = 8 mod 64)
+//   Q, K-contiguous  lds[mn*S + k]: S = BK + 8   (2 S = 16 or 48 mod 64: the
+//      four columns read by a quarter-wave are 16 banks apart)
 // ---------------------------------------------------------------------------
-template <int BMN, int BK, bool KC>
+template <int BMN, int BK, bool KC, bool ROLE_P>
 struct OpTile {
   static constexpr int LC = KC ? BK : BMN;  // extent along the contiguous dim
   static constexpr int LS = KC ? BMN : BK;  // extent along the strided dim
-  static constexpr int S = KC ? BK + 2 : BMN + 4;
+  static constexpr int S = KC ? (ROLE_P ? BK + 2 : BK + 8) : (ROLE_P ? BMN + 8 : BMN + 2);
   static constexpr int ELEMS = LS * S;
 };
 
+// A is K-contiguous iff transposed; B is K-contiguous iff not transposed.
 template <class CF, bool TA, bool TB>
 struct Smem {
-  using TAt = OpTile<CF::BM, CF::BK, TA>;    // A is K-contiguous iff transposed
-  using TBt = OpTile<CF::BN, CF::BK, !TB>;   // B is K-contiguous iff not transposed
+  using TAt = OpTile<CF::BM, CF::BK, TA, !CF::SWAP>;
+  using TBt = OpTile<CF::BN, CF::BK, !TB, CF::SWAP>;
   static constexpr int A_ELEMS = TAt::ELEMS, B_ELEMS = TBt::ELEMS;
   static constexpr int TOTAL = 2 * (A_ELEMS + B_ELEMS);  // double buffered
 };
@@ -80,9 +112,8 @@ struct SmemMax {
 
 // Global -> register -> LDS copy of one operand tile, NT threads, 16 bytes
 // (two consecutive doubles along the contiguous dim) per thread per step.
-template <int BMN, int BK, bool KC, int NT>
+template <class T, int NT>
 struct OpLoader {
-  using T = OpTile<BMN, BK, KC>;
   static constexpr int PAIRS = T::LC * T::LS / 2;
   static constexpr int PER = PAIRS / NT;
   static_assert(PAIRS % NT == 0, "tile not divisible among threads");
@@ -90,14 +121,15 @@ struct OpLoader {
 
   // base: operand matrix; ld: its leading dimension; (c0, s0): tile origin
   // along the contiguous / strided dims; (cext, sext): matrix extents there.
-  __device__ __forceinline__ void load(const double* __restrict__ base, int64_t ld, int c0, int s0,
-                                       int cext, int sext, bool fast, int tid) {
+  // `fast`: the whole tile is inside the matrix and 16-byte aligned.
+  __device__ __forceinline__ void load(gcptr base, int64_t ld, int c0, int s0, int cext, int sext,
+                                       bool fast, int tid) {
     if (fast) {
 #pragma unroll
       for (int it = 0; it < PER; ++it) {
         const int e = 2 * (tid + it * NT);
         const int cc = e % T::LC, ss = e / T::LC;
-        v[it] = *reinterpret_cast<const d2*>(base + (c0 + cc) + (int64_t)(s0 + ss) * ld);
+        v[it] = *(const AS_GLOBAL d2*)(base + (c0 + cc) + (int64_t)(s0 + ss) * ld);
       }
     } else {
 #pragma unroll
@@ -105,7 +137,7 @@ struct OpLoader {
         const int e = 2 * (tid + it * NT);
         const int cc = e % T::LC, ss = e / T::LC;
         const int c = c0 + cc, s = s0 + ss;
-        const double* p = base + c + (int64_t)s * ld;
+        gcptr p = base + c + (int64_t)s * ld;
         const bool sok = s < sext;
         v[it].x = (sok && c < cext) ? p[0] : 0.0;
         v[it].y = (sok && c + 1 < cext) ? p[1] : 0.0;
@@ -113,37 +145,53 @@ struct OpLoader {
     }
   }
 
-  __device__ __forceinline__ void store(double* lds, int tid) const {
+  __device__ __forceinline__ void store(lptr lds, int tid) const {
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
       const int e = 2 * (tid + it * NT);
       const int cc = e % T::LC, ss = e / T::LC;
-      *reinterpret_cast<d2*>(lds + ss * T::S + cc) = v[it];
+      *(AS_LDS d2*)(lds + ss * T::S + cc) = v[it];
     }
   }
 };
 
-// Reads this lane's fragments for NB 16-wide blocks starting at `mn0` and the
-// 16-wide k slice starting at `kk`: f[b][t] = op(X)(mn0 + 16 b + l%16,
-// kk + 4 (l/16) + t).
-template <int BMN, int BK, bool KC, int NB>
-__device__ __forceinline__ void read_frags(const double* lds, int mn0, int kk, int lane,
-                                           double (&f)[NB][4]) {
-  using T = OpTile<BMN, BK, KC>;
-  const int r = lane & 15, g = lane >> 4;
-  if constexpr (KC) {
+// k offset (within a 16-slice) of lane group s for instruction t.
+__device__ __forceinline__ int kperm(int s, int t) { return 2 * s + 8 * (t >> 1) + (t & 1); }
+
+// P-role fragments of NB slabs for the instruction pair (2 tp, 2 tp + 1):
+// f[b][u] = X(mn0 + 16 b + l%16, kk + kperm(l/16, 2 tp + u)).
+template <class T, int NB, bool KC>
+__device__ __forceinline__ void read_p(lcptr lds, int mn0, int kk, int tp, int lane,
+                                       double (&f)[NB][2]) {
+  const int r = lane & 15, s = lane >> 4;
+  const int k = kk + 2 * s + 8 * tp;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const double* p = lds + (mn0 + 16 * b + r) * T::S + kk + 4 * g;
-      const d2 lo = *reinterpret_cast<const d2*>(p);
-      const d2 hi = *reinterpret_cast<const d2*>(p + 2);
-      f[b][0] = lo.x; f[b][1] = lo.y; f[b][2] = hi.x; f[b][3] = hi.y;
+  for (int b = 0; b < NB; ++b) {
+    if constexpr (KC) {
+      const d2 x = *(const AS_LDS d2*)(lds + (mn0 + 16 * b + r) * T::S + k);
+      f[b][0] = x.x; f[b][1] = x.y;
+    } else {
+      f[b][0] = lds[k * T::S + mn0 + 16 * b + r];
+      f[b][1] = lds[(k + 1) * T::S + mn0 + 16 * b + r];
     }
-  } else {
+  }
+}
+
+// Q-role fragments of NG groups: f[g][u] = X(mn0 + 4 g + l%4, kk + kperm(l/16, 2 tp + u)).
+template <class T, int NG, bool KC>
+__device__ __forceinline__ void read_q(lcptr lds, int mn0, int kk, int tp, int lane,
+                                       double (&f)[NG][2]) {
+  const int j = lane & 3, s = lane >> 4;
+  const int k = kk + 2 * s + 8 * tp;
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) f[b][t] = lds[(kk + 4 * g + t) * T::S + mn0 + 16 * b + r];
+  for (int g = 0; g < NG; ++g) {
+    if constexpr (KC) {
+      const d2 x = *(const AS_LDS d2*)(lds + (mn0 + 4 * g + j) * T::S + k);
+      f[g][0] = x.x; f[g][1] = x.y;
+    } else {
+      f[g][0] = lds[k * T::S + mn0 + 4 * g + j];
+      f[g][1] = lds[(k + 1) * T::S + mn0 + 4 * g + j];
+    }
   }
 }
 
@@ -158,14 +206,18 @@ __device__ __forceinline__ bool aligned16(const void* p) {
 // beta == 1).  Every thread of the workgroup must call this (it synchronises).
 // ---------------------------------------------------------------------------
 template <class CF, bool TA, bool TB>
-__device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t lda,
-                                          const double* __restrict__ B, int64_t ldb,
-                                          double* __restrict__ C, int64_t ldc, int M, int N, int K,
-                                          double alpha, double beta, int tm, int tn,
-                                          double* lds) {
+__device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const double* B_,
+                                          int64_t ldb, double* C_, int64_t ldc, int M, int N, int K,
+                                          double alpha, double beta, int tm, int tn, lptr lds) {
+  const gcptr A = (gcptr)A_;
+  const gcptr B = (gcptr)B_;
+  const gptr C = (gptr)C_;
   using SM = Smem<CF, TA, TB>;
-  using LA = OpLoader<CF::BM, CF::BK, TA, CF::NT>;
-  using LB = OpLoader<CF::BN, CF::BK, !TB, CF::NT>;
+  using TAt = typename SM::TAt;
+  using TBt = typename SM::TBt;
+  using LA = OpLoader<TAt, CF::NT>;
+  using LB = OpLoader<TBt, CF::NT>;
+  constexpr bool SW = CF::SWAP;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave % CF::WAVES_M) * CF::WM;
@@ -173,83 +225,89 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t 
   const int m0 = tm * CF::BM, n0 = tn * CF::BN;
   const bool use_product = !(alpha == 0.0 || K == 0);
 
-  d4 acc[CF::FM][CF::FN];
+  double acc[CF::FP][CF::GQ];
 #pragma unroll
-  for (int i = 0; i < CF::FM; ++i)
+  for (int i = 0; i < CF::FP; ++i)
 #pragma unroll
-    for (int j = 0; j < CF::FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < CF::GQ; ++j) acc[i][j] = 0.0;
 
   if (use_product) {
-    double* la[2] = {lds, lds + SM::A_ELEMS};
-    double* lb[2] = {lds + 2 * SM::A_ELEMS, lds + 2 * SM::A_ELEMS + SM::B_ELEMS};
-    // Extents of each operand along its (contiguous, strided) dims and the
-    // origin of this tile along them for k-slice k0.
+    const lptr la0 = lds, lb0 = lds + 2 * SM::A_ELEMS;
     const int a_cext = TA ? K : M, a_sext = TA ? M : K;
     const int b_cext = TB ? N : K, b_sext = TB ? K : N;
-    const bool a_vec = aligned16(A) && (lda % 2 == 0);
-    const bool b_vec = aligned16(B) && (ldb % 2 == 0);
-    const bool a_mn_full = m0 + CF::BM <= M;
-    const bool b_mn_full = n0 + CF::BN <= N;
+    const bool a_vec = aligned16(A_) && (lda % 2 == 0) && (m0 + CF::BM <= M);
+    const bool b_vec = aligned16(B_) && (ldb % 2 == 0) && (n0 + CF::BN <= N);
     LA ra;
     LB rb;
     auto load = [&](int k0) {
       const bool kfull = k0 + CF::BK <= K;
-      if (TA) ra.load(A, lda, k0, m0, a_cext, a_sext, a_vec && kfull && a_mn_full, tid);
-      else    ra.load(A, lda, m0, k0, a_cext, a_sext, a_vec && kfull && a_mn_full, tid);
-      if (TB) rb.load(B, ldb, n0, k0, b_cext, b_sext, b_vec && kfull && b_mn_full, tid);
-      else    rb.load(B, ldb, k0, n0, b_cext, b_sext, b_vec && kfull && b_mn_full, tid);
+      if (TA) ra.load(A, lda, k0, m0, a_cext, a_sext, a_vec && kfull, tid);
+      else    ra.load(A, lda, m0, k0, a_cext, a_sext, a_vec && kfull, tid);
+      if (TB) rb.load(B, ldb, n0, k0, b_cext, b_sext, b_vec && kfull, tid);
+      else    rb.load(B, ldb, k0, n0, b_cext, b_sext, b_vec && kfull, tid);
     };
     const int nk = (K + CF::BK - 1) / CF::BK;
     load(0);
-    ra.store(la[0], tid);
-    rb.store(lb[0], tid);
+    ra.store(la0, tid);
+    rb.store(lb0, tid);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
       const int cur = kt & 1;
       if (kt + 1 < nk) load((kt + 1) * CF::BK);
+      const lcptr la_cur = la0 + cur * SM::A_ELEMS, lb_cur = lb0 + cur * SM::B_ELEMS;
+      const lcptr lp = SW ? lb_cur : la_cur;
+      const lcptr lq = SW ? la_cur : lb_cur;
+      const int p0 = SW ? wn0 : wm0, q0 = SW ? wm0 : wn0;
 #pragma unroll
       for (int kk = 0; kk < CF::BK; kk += 16) {
-        double fa[CF::FM][4], fb[CF::FN][4];
-        read_frags<CF::BM, CF::BK, TA, CF::FM>(la[cur], wm0, kk, lane, fa);
-        read_frags<CF::BN, CF::BK, !TB, CF::FN>(lb[cur], wn0, kk, lane, fb);
+        if (kt * CF::BK + kk >= K) break;  // whole 16-slices only, the same in every class
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int tp = 0; tp < 2; ++tp) {
+          double fp[CF::FP][2], fq[CF::GQ][2];
+          if constexpr (SW) {
+            read_p<TBt, CF::FP, !TB>(lp, p0, kk, tp, lane, fp);
+            read_q<TAt, CF::GQ, TA>(lq, q0, kk, tp, lane, fq);
+          } else {
+            read_p<TAt, CF::FP, TA>(lp, p0, kk, tp, lane, fp);
+            read_q<TBt, CF::GQ, !TB>(lq, q0, kk, tp, lane, fq);
+          }
 #pragma unroll
-          for (int i = 0; i < CF::FM; ++i)
+          for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int j = 0; j < CF::FN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j][t], fa[i][t], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < CF::FP; ++i)
+#pragma unroll
+              for (int j = 0; j < CF::GQ; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(fp[i][u], fq[j][u], acc[i][j], 0, 0, 0);
+        }
       }
       if (kt + 1 < nk) {
-        ra.store(la[cur ^ 1], tid);
-        rb.store(lb[cur ^ 1], tid);
+        ra.store(la0 + (cur ^ 1) * SM::A_ELEMS, tid);
+        rb.store(lb0 + (cur ^ 1) * SM::B_ELEMS, tid);
       }
       __syncthreads();
     }
   }
 
-  // Epilogue: lane holds C(m0 + wm0 + 16 i + l%16, n0 + wn0 + 16 j + l/16 + 4 v).
-  const int r = lane & 15, g = lane >> 4;
+  // Epilogue.  Lane 16 i + 4 b + j holds P index p0 + 16 fp + 4 b + i and
+  // Q index q0 + 4 g + j of acc[fp][g].
+  const int li = lane >> 4, lb4 = (lane >> 2) & 3, lj = lane & 3;
+  const int pofs = 4 * lb4 + li;
 #pragma unroll
-  for (int i = 0; i < CF::FM; ++i) {
-    const int row = m0 + wm0 + 16 * i + r;
-    if (row >= M) continue;
+  for (int i = 0; i < CF::FP; ++i) {
 #pragma unroll
-    for (int j = 0; j < CF::FN; ++j) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = n0 + wn0 + 16 * j + g + 4 * v;
-        if (col >= N) continue;
-        double* p = C + row + (int64_t)col * ldc;
-        if (use_product) {
-          double x = alpha * acc[i][j][v];
-          if (beta != 0.0) x = x + beta * (*p);
-          *p = x;
-        } else if (beta == 0.0) {
-          *p = 0.0;
-        } else if (beta != 1.0) {
-          *p = beta * (*p);
-        }
+    for (int j = 0; j < CF::GQ; ++j) {
+      const int row = SW ? m0 + wm0 + 4 * j + lj : m0 + wm0 + 16 * i + pofs;
+      const int col = SW ? n0 + wn0 + 16 * i + pofs : n0 + wn0 + 4 * j + lj;
+      if (row >= M || col >= N) continue;
+      const gptr p = C + row + (int64_t)col * ldc;
+      if (use_product) {
+        double x = alpha * acc[i][j];
+        if (beta != 0.0) x = x + beta * (*p);
+        *p = x;
+      } else if (beta == 0.0) {
+        *p = 0.0;
+      } else if (beta != 1.0) {
+        *p = beta * (*p);
       }
     }
   }
@@ -277,7 +335,7 @@ __global__ __launch_bounds__(CF::NT) void k_uniform(
   const int t = (int)(id - inst * tiles_per_inst);
   const int tm = t % tiles_m, tn = t / tiles_m;
   gemm_tile<CF, TA, TB>(Ap[inst], lda, Bp[inst], ldb, Cp[inst], ldc, M, N, K, alpha, beta, tm,
-                        tn, lds);
+                        tn, (lptr)lds);
 }
 
 template <class CF, bool TA, bool TB>
@@ -517,7 +575,7 @@ __global__ __launch_bounds__(CfgVb::NT) void k_vb_exec(
     const int tiles_m = (mi + CfgVb::BM - 1) / CfgVb::BM;
     const int t = (int)(q - prefix[i]);
     gemm_tile<CfgVb, TA, TB>(Ap[i], lda[i], Bp[i], ldb[i], Cp[i], ldc[i], mi, ni, ki, alpha, beta,
-                             t % tiles_m, t / tiles_m, lds);
+                             t % tiles_m, t / tiles_m, (lptr)lds);
   }
 }
 

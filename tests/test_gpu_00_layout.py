@@ -22,3 +22,29 @@ def test_mfma_lane_layout():
     D = Am @ Bm + Cm
     want = np.stack([D[lanes // 16 + 4 * v, lanes % 16] for v in range(4)], axis=1)
     assert np.array_equal(d, want)
+
+
+def test_mfma_4x4x4_lane_layout():
+    """Pins the layout of v_mfma_f64_4x4x4_4b_f64 the tile kernels use: for
+    block b, lane 16 s + 4 b + i holds A_b(i, s), lane 16 s + 4 b + j holds
+    B_b(s, j), and D_b(i, j) (and C_b(i, j)) live in lane 16 i + 4 b + j."""
+    from paper_2203_09353_amd import microbench
+    rng = np.random.default_rng(1)
+    A = rng.integers(-8, 9, (4, 4, 4)).astype(float)   # [b, i, s]
+    B = rng.integers(-8, 9, (4, 4, 4)).astype(float)   # [b, s, j]
+    C = rng.integers(-8, 9, (4, 4, 4)).astype(float)   # [b, i, j]
+    a = np.zeros(64); b = np.zeros(64); c = np.zeros(64)
+    for blk in range(4):
+        for x in range(4):
+            for y in range(4):
+                a[16 * y + 4 * blk + x] = A[blk, x, y]
+                b[16 * x + 4 * blk + y] = B[blk, x, y]
+                c[16 * x + 4 * blk + y] = C[blk, x, y]
+    d = microbench.mfma4_once(a, b, c).numpy()
+    D = A @ B + C
+    want = np.zeros(64)
+    for blk in range(4):
+        for i in range(4):
+            for j in range(4):
+                want[16 * i + 4 * blk + j] = D[blk, i, j]
+    assert np.array_equal(d, want)
