@@ -40,14 +40,17 @@ class BgemmError(RuntimeError):
         super().__init__(msg)
 
 
-def lib():
-    """Loads libbgemm.so (raises if it has not been built)."""
+def lib(path: str | None = None):
+    """Loads libbgemm.so (raises if it has not been built).  ``path`` selects
+    another build of the same interface (e.g. a tuning variant); it must be
+    given before the first call."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
+    path = path or LIB_PATH
+    if not os.path.exists(path):
         raise RuntimeError("libbgemm.so not built: run python -m paper_2203_09353_amd.build")
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     vp, i, d, c = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_char
     L.bg_version.restype = i
     L.bg_version.argtypes = []

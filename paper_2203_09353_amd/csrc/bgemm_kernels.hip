@@ -31,6 +31,8 @@
 // feeds two instructions with one 16-byte LDS read.  Every tile class walks k
 // in the same slices and order, so a given element of C gets the same bits
 // from every class, alone or in any batch.
+#include <type_traits>
+
 #include "bgemm_internal.h"
 
 namespace bg {
@@ -52,10 +54,17 @@ typedef const AS_LDS double* lcptr;
 // Tile configurations: C tile BM x BN per workgroup, BK of k per LDS stage,
 // wave tile WM x WN, SWAP selects the C^T form (P = op(B)^T, Q = op(A)).
 // ---------------------------------------------------------------------------
-template <int BM_, int BN_, int BK_, int WM_, int WN_, bool SWAP_>
+template <int BM_, int BN_, int BK_, int WM_, int WN_, bool SWAP_, int NSTAGE_ = 2,
+          bool CPRE_ = false, int SKIP_ = 0>
 struct Cfg {
   static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
   static constexpr bool SWAP = SWAP_;
+  static constexpr int NSTAGE = NSTAGE_;      // LDS buffers (2: double buffered)
+  static constexpr bool CPRE = CPRE_;         // read C (beta != 0) before the k loop
+  // Work skipped on edge tiles: 0 none, 1 waves whose region lies outside C,
+  // 2 also single instructions whose 16 x 4 output lies outside C.
+  static constexpr int SKIP = SKIP_;
+  static_assert(NSTAGE == 1 || NSTAGE == 2, "one or two LDS stages");
   static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN;
   static constexpr int NT = WAVES_M * WAVES_N * 64;
   static constexpr int WP = SWAP ? WN : WM;   // wave extent along P
@@ -66,9 +75,20 @@ struct Cfg {
   static_assert(BK % 16 == 0, "BK must be a multiple of 16");
 };
 
-using Cfg32 = Cfg<32, 32, 32, 32, 32, false>;
-using Cfg64 = Cfg<64, 64, 32, 64, 16, false>;
-using Cfg128 = Cfg<128, 128, 16, 32, 64, true>;
+// Shapes per size class (BM, BN, BK, WM, WN, SWAP); the BG_CFG* macros let a
+// tuning build try other shapes without editing the source.
+#ifndef BG_CFG32
+#define BG_CFG32 32, 32, 32, 32, 32, false
+#endif
+#ifndef BG_CFG64
+#define BG_CFG64 64, 64, 16, 32, 32, true, 2, true
+#endif
+#ifndef BG_CFG128
+#define BG_CFG128 128, 64, 16, 16, 64, true
+#endif
+using Cfg32 = Cfg<BG_CFG32>;
+using Cfg64 = Cfg<BG_CFG64>;
+using Cfg128 = Cfg<BG_CFG128>;
 
 // ---------------------------------------------------------------------------
 // Operand tiles in LDS.  An operand tile spans BMN values of its product
@@ -99,16 +119,9 @@ struct Smem {
   using TAt = OpTile<CF::BM, CF::BK, TA, !CF::SWAP>;
   using TBt = OpTile<CF::BN, CF::BK, !TB, CF::SWAP>;
   static constexpr int A_ELEMS = TAt::ELEMS, B_ELEMS = TBt::ELEMS;
-  static constexpr int TOTAL = 2 * (A_ELEMS + B_ELEMS);  // double buffered
+  static constexpr int TOTAL = CF::NSTAGE * (A_ELEMS + B_ELEMS);
 };
 
-template <class CF>
-struct SmemMax {
-  static constexpr int a = Smem<CF, false, false>::TOTAL, b = Smem<CF, false, true>::TOTAL;
-  static constexpr int c = Smem<CF, true, false>::TOTAL, d = Smem<CF, true, true>::TOTAL;
-  static constexpr int ab = a > b ? a : b, cd = c > d ? c : d;
-  static constexpr int VALUE = ab > cd ? ab : cd;
-};
 
 // Global -> register -> LDS copy of one operand tile, NT threads, 16 bytes
 // (two consecutive doubles along the contiguous dim) per thread per step.
@@ -231,8 +244,31 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
 #pragma unroll
     for (int j = 0; j < CF::GQ; ++j) acc[i][j] = 0.0;
 
+  // Position of acc[i][j] in C.  Lane 16 li + 4 lb4 + lj holds P index
+  // p0 + 16 i + 4 lb4 + li and Q index q0 + 4 j + lj.
+  const int li = lane >> 4, lb4 = (lane >> 2) & 3, lj = lane & 3;
+  const int pofs = 4 * lb4 + li;
+  auto c_row = [&](int i, int j) { return SW ? m0 + wm0 + 4 * j + lj : m0 + wm0 + 16 * i + pofs; };
+  auto c_col = [&](int i, int j) { return SW ? n0 + wn0 + 16 * i + pofs : n0 + wn0 + 4 * j + lj; };
+
+  // With beta != 0 the C tile is read up front so that its latency overlaps
+  // the contraction instead of following it.
+  constexpr bool CP = CF::CPRE;
+  double cpre[CP ? CF::FP : 1][CP ? CF::GQ : 1];
+  const bool prefetch_c = CP && use_product && beta != 0.0;
+  if (prefetch_c) {
+#pragma unroll
+    for (int i = 0; i < CF::FP; ++i)
+#pragma unroll
+      for (int j = 0; j < CF::GQ; ++j) {
+        const int row = c_row(i, j), col = c_col(i, j);
+        cpre[CP ? i : 0][CP ? j : 0] =
+            (row < M && col < N) ? C[row + (int64_t)col * ldc] : 0.0;
+      }
+  }
+
   if (use_product) {
-    const lptr la0 = lds, lb0 = lds + 2 * SM::A_ELEMS;
+    const lptr la0 = lds, lb0 = lds + CF::NSTAGE * SM::A_ELEMS;
     const int a_cext = TA ? K : M, a_sext = TA ? M : K;
     const int b_cext = TB ? N : K, b_sext = TB ? K : N;
     const bool a_vec = aligned16(A_) && (lda % 2 == 0) && (m0 + CF::BM <= M);
@@ -251,58 +287,75 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
     ra.store(la0, tid);
     rb.store(lb0, tid);
     __syncthreads();
+    const int p0 = SW ? wn0 : wm0, q0 = SW ? wm0 : wn0;
+    // Valid extents of this wave's region along P and Q.  On edge tiles the
+    // instructions whose 16 P indices or 4 Q indices all fall outside C are
+    // skipped (wave-uniform tests); interior waves run without tests.
+    const int p_ext = SW ? N - n0 - wn0 : M - m0 - wm0;
+    const int q_ext = SW ? M - m0 - wm0 : N - n0 - wn0;
+    const bool interior = p_ext >= CF::WP && q_ext >= CF::WQ;
+    auto slice = [&](lcptr lp, lcptr lq, int kk, auto edge) {
+      constexpr bool EDGE = decltype(edge)::value;
+#pragma unroll
+      for (int tp = 0; tp < 2; ++tp) {
+        double fp[CF::FP][2], fq[CF::GQ][2];
+        if constexpr (SW) {
+          read_p<TBt, CF::FP, !TB>(lp, p0, kk, tp, lane, fp);
+          read_q<TAt, CF::GQ, TA>(lq, q0, kk, tp, lane, fq);
+        } else {
+          read_p<TAt, CF::FP, TA>(lp, p0, kk, tp, lane, fp);
+          read_q<TBt, CF::GQ, !TB>(lq, q0, kk, tp, lane, fq);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int i = 0; i < CF::FP; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::GQ; ++j)
+              if (!EDGE || (16 * i < p_ext && 4 * j < q_ext))
+                acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(fp[i][u], fq[j][u], acc[i][j], 0, 0, 0);
+      }
+    };
     for (int kt = 0; kt < nk; ++kt) {
-      const int cur = kt & 1;
+      const int cur = CF::NSTAGE == 2 ? (kt & 1) : 0;
       if (kt + 1 < nk) load((kt + 1) * CF::BK);
       const lcptr la_cur = la0 + cur * SM::A_ELEMS, lb_cur = lb0 + cur * SM::B_ELEMS;
       const lcptr lp = SW ? lb_cur : la_cur;
       const lcptr lq = SW ? la_cur : lb_cur;
-      const int p0 = SW ? wn0 : wm0, q0 = SW ? wm0 : wn0;
 #pragma unroll
       for (int kk = 0; kk < CF::BK; kk += 16) {
         if (kt * CF::BK + kk >= K) break;  // whole 16-slices only, the same in every class
-#pragma unroll
-        for (int tp = 0; tp < 2; ++tp) {
-          double fp[CF::FP][2], fq[CF::GQ][2];
-          if constexpr (SW) {
-            read_p<TBt, CF::FP, !TB>(lp, p0, kk, tp, lane, fp);
-            read_q<TAt, CF::GQ, TA>(lq, q0, kk, tp, lane, fq);
-          } else {
-            read_p<TAt, CF::FP, TA>(lp, p0, kk, tp, lane, fp);
-            read_q<TBt, CF::GQ, !TB>(lq, q0, kk, tp, lane, fq);
-          }
-#pragma unroll
-          for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int i = 0; i < CF::FP; ++i)
-#pragma unroll
-              for (int j = 0; j < CF::GQ; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(fp[i][u], fq[j][u], acc[i][j], 0, 0, 0);
+        if constexpr (CF::SKIP == 2) {
+          if (interior) slice(lp, lq, kk, std::false_type{});
+          else if (p_ext > 0 && q_ext > 0) slice(lp, lq, kk, std::true_type{});
+        } else if constexpr (CF::SKIP == 1) {
+          if (p_ext > 0 && q_ext > 0) slice(lp, lq, kk, std::false_type{});
+        } else {
+          slice(lp, lq, kk, std::false_type{});
         }
       }
       if (kt + 1 < nk) {
-        ra.store(la0 + (cur ^ 1) * SM::A_ELEMS, tid);
-        rb.store(lb0 + (cur ^ 1) * SM::B_ELEMS, tid);
+        if (CF::NSTAGE == 1) __syncthreads();  // every wave is done reading the stage
+        const int nxt = CF::NSTAGE == 2 ? (cur ^ 1) : 0;
+        ra.store(la0 + nxt * SM::A_ELEMS, tid);
+        rb.store(lb0 + nxt * SM::B_ELEMS, tid);
       }
       __syncthreads();
     }
   }
 
-  // Epilogue.  Lane 16 i + 4 b + j holds P index p0 + 16 fp + 4 b + i and
-  // Q index q0 + 4 g + j of acc[fp][g].
-  const int li = lane >> 4, lb4 = (lane >> 2) & 3, lj = lane & 3;
-  const int pofs = 4 * lb4 + li;
+  // Epilogue
 #pragma unroll
   for (int i = 0; i < CF::FP; ++i) {
 #pragma unroll
     for (int j = 0; j < CF::GQ; ++j) {
-      const int row = SW ? m0 + wm0 + 4 * j + lj : m0 + wm0 + 16 * i + pofs;
-      const int col = SW ? n0 + wn0 + 16 * i + pofs : n0 + wn0 + 4 * j + lj;
+      const int row = c_row(i, j), col = c_col(i, j);
       if (row >= M || col >= N) continue;
       const gptr p = C + row + (int64_t)col * ldc;
       if (use_product) {
         double x = alpha * acc[i][j];
-        if (beta != 0.0) x = x + beta * (*p);
+        if (beta != 0.0)
+          x = x + beta * (prefetch_c ? cpre[CP ? i : 0][CP ? j : 0] : *p);
         *p = x;
       } else if (beta == 0.0) {
         *p = 0.0;
@@ -327,7 +380,7 @@ __global__ __launch_bounds__(CF::NT) void k_uniform(
     const double* const* __restrict__ Bp, int64_t ldb, double beta,
     double* const* __restrict__ Cp, int64_t ldc, int tiles_m, int tiles_per_inst,
     int64_t total_tiles, int64_t per_xcd) {
-  __shared__ double lds[SmemMax<CF>::VALUE];
+  __shared__ double lds[Smem<CF, TA, TB>::TOTAL];
   const int64_t bid = blockIdx.x;
   const int64_t id = (bid % NUM_XCD) * per_xcd + bid / NUM_XCD;
   if (id >= total_tiles) return;
@@ -409,22 +462,44 @@ hipError_t launch_scale(double beta, double* const* C, int64_t ldc, int m, int n
 // ---------------------------------------------------------------------------
 // Variable-size batch (the paper, Section II: each GEMM gets its own 2-D grid
 // of tiles, sizes differ per instance).  Sizes live on the device, so the
-// whole plan is made there:
-//   1. k_vb_count: validate each instance (info), count its C tiles, and
-//      scan the counts within each block of 256 instances;
-//   2. k_vb_blocks: scan the block totals (one workgroup), reset the queue;
-//   3. k_vb_finish: global exclusive prefix P[i] and, when it fits, a map
-//      tile -> instance;
-//   4. k_vb_exec: a persistent grid; each workgroup pops tile numbers from an
-//      atomic counter until the queue is empty.
+// whole plan is made there.  Each instance is assigned one of three tile
+// classes (128 x 64, 64 x 64, 32 x 32) by the padded work its C grid costs;
+// each class gets its own tile queue, and a persistent kernel per class, in
+// decreasing tile size, pops tiles from it:
+//   1. k_vb_count: validate each instance (info), choose its class, count its
+//      C tiles, and scan the counts of each class within blocks of 256;
+//   2. k_vb_blocks: scan the block totals of each class (one workgroup),
+//      reset the queues;
+//   3. k_vb_finish: per-class exclusive prefix P_c[i] over instances;
+//   4. k_vb_map: when it fits in the workspace, a map tile -> instance;
+//   5. k_vb_exec (x3): a persistent grid per class; each workgroup pops tile
+//      numbers from its class's atomic counter until the queue is empty,
+//      fetching the next number while it computes the current tile.
 // ---------------------------------------------------------------------------
-using CfgVb = Cfg64;
+#ifndef BG_CFGVB_L
+#define BG_CFGVB_L 128, 64, 16, 32, 32, true
+#endif
+#ifndef BG_CFGVB_M
+#define BG_CFGVB_M 64, 64, 16, 32, 32, true, 2, true
+#endif
+#ifndef BG_CFGVB_S
+#define BG_CFGVB_S 32, 32, 16, 32, 32, false, 2, true
+#endif
+// relative cost per padded C element of the three classes, for the choice
+#ifndef BG_VB_WEIGHTS
+#define BG_VB_WEIGHTS 1.0f, 1.15f, 1.6f
+#endif
+using CfgVbL = Cfg<BG_CFGVB_L>;
+using CfgVbM = Cfg<BG_CFGVB_M>;
+using CfgVbS = Cfg<BG_CFGVB_S>;
+constexpr int VB_NC = 3;
 constexpr int PLAN_BLOCK = 256;
+constexpr int VB_CTRL = VB_NC + VB_NC * 8;  // totals, then one queue head per (class, XCD)
 
 struct VbLayout {
-  int64_t* prefix;   // [batch + 1]
-  int64_t* bsum;     // [nblocks]
-  int64_t* ctrl;     // [0] total tiles, [1] queue head
+  int64_t* prefix;   // [VB_NC][batch + 1]
+  int64_t* bsum;     // [VB_NC][nblocks]
+  int64_t* ctrl;     // [0..2] tiles per class, then queue heads [class][xcd]
   int* map;          // [map_cap]
   int64_t map_cap;
 };
@@ -433,16 +508,17 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t vbatched_workspace_bytes(int batch) {
   const size_t nb = ((size_t)batch + PLAN_BLOCK - 1) / PLAN_BLOCK;
-  return align256(((size_t)batch + 1) * 8) + align256(nb * 8) + align256(64);
+  return align256(VB_NC * ((size_t)batch + 1) * 8) + align256(VB_NC * nb * 8) +
+         align256(VB_CTRL * 8);
 }
 
 static VbLayout vb_layout(const VbWorkspace& ws, int batch) {
   VbLayout L;
   char* p = (char*)ws.base;
   const size_t nb = ((size_t)batch + PLAN_BLOCK - 1) / PLAN_BLOCK;
-  L.prefix = (int64_t*)p; p += align256(((size_t)batch + 1) * 8);
-  L.bsum = (int64_t*)p; p += align256(nb * 8);
-  L.ctrl = (int64_t*)p; p += align256(64);
+  L.prefix = (int64_t*)p; p += align256(VB_NC * ((size_t)batch + 1) * 8);
+  L.bsum = (int64_t*)p; p += align256(VB_NC * nb * 8);
+  L.ctrl = (int64_t*)p; p += align256(VB_CTRL * 8);
   const size_t used = (size_t)(p - (char*)ws.base);
   L.map = (int*)p;
   L.map_cap = used < ws.bytes ? (int64_t)((ws.bytes - used) / sizeof(int)) : 0;
@@ -463,61 +539,92 @@ __device__ __forceinline__ int vb_check(bool ta, bool tb, int m, int n, int k, i
   return 0;
 }
 
+template <class CF>
+__device__ __forceinline__ int64_t vb_tiles(int m, int n) {
+  return (int64_t)((m + CF::BM - 1) / CF::BM) * ((n + CF::BN - 1) / CF::BN);
+}
+
+// Class with the least weighted padded C area; ties go to the larger tile.
+__device__ __forceinline__ int vb_class(int m, int n, int64_t* tiles) {
+  const float w[VB_NC] = {BG_VB_WEIGHTS};
+  const int64_t t[VB_NC] = {vb_tiles<CfgVbL>(m, n), vb_tiles<CfgVbM>(m, n),
+                            vb_tiles<CfgVbS>(m, n)};
+  const float area[VB_NC] = {(float)(CfgVbL::BM * CfgVbL::BN), (float)(CfgVbM::BM * CfgVbM::BN),
+                             (float)(CfgVbS::BM * CfgVbS::BN)};
+  int best = 0;
+  float cost = w[0] * area[0] * (float)t[0];
+  for (int c = 1; c < VB_NC; ++c) {
+    const float x = w[c] * area[c] * (float)t[c];
+    if (x < cost) { cost = x; best = c; }
+  }
+  *tiles = t[best];
+  return best;
+}
+
 __global__ __launch_bounds__(PLAN_BLOCK) void k_vb_count(
     bool ta, bool tb, const int* __restrict__ m, const int* __restrict__ n,
     const int* __restrict__ k, const int* __restrict__ lda, const int* __restrict__ ldb,
     const int* __restrict__ ldc, double alpha, double beta, int batch, int* __restrict__ info,
     int64_t* __restrict__ prefix, int64_t* __restrict__ bsum) {
-  __shared__ int64_t sh[PLAN_BLOCK];
+  __shared__ int64_t sh[VB_NC][PLAN_BLOCK];
   const int i = blockIdx.x * PLAN_BLOCK + threadIdx.x;
   int64_t tiles = 0;
+  int cls = 0;
   if (i < batch) {
     const int mi = m[i], ni = n[i], ki = k[i];
     const int st = vb_check(ta, tb, mi, ni, ki, lda[i], ldb[i], ldc[i]);
     if (info) info[i] = st;
     const bool noop = (alpha == 0.0 || ki == 0) && beta == 1.0;
-    if (st == 0 && mi > 0 && ni > 0 && !noop)
-      tiles = (int64_t)((mi + CfgVb::BM - 1) / CfgVb::BM) * ((ni + CfgVb::BN - 1) / CfgVb::BN);
+    if (st == 0 && mi > 0 && ni > 0 && !noop) cls = vb_class(mi, ni, &tiles);
   }
-  // inclusive scan within the block (Hillis-Steele in LDS)
-  sh[threadIdx.x] = tiles;
+  int64_t mine[VB_NC];
+  for (int c = 0; c < VB_NC; ++c) {
+    mine[c] = (c == cls) ? tiles : 0;
+    sh[c][threadIdx.x] = mine[c];
+  }
   __syncthreads();
-  for (int off = 1; off < PLAN_BLOCK; off <<= 1) {
-    const int64_t x = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+  for (int off = 1; off < PLAN_BLOCK; off <<= 1) {  // inclusive scans (Hillis-Steele)
+    int64_t x[VB_NC];
+    for (int c = 0; c < VB_NC; ++c) x[c] = threadIdx.x >= off ? sh[c][threadIdx.x - off] : 0;
     __syncthreads();
-    sh[threadIdx.x] += x;
+    for (int c = 0; c < VB_NC; ++c) sh[c][threadIdx.x] += x[c];
     __syncthreads();
   }
-  if (i < batch) prefix[i] = sh[threadIdx.x] - tiles;  // exclusive, block-local
-  if (threadIdx.x == PLAN_BLOCK - 1) bsum[blockIdx.x] = sh[PLAN_BLOCK - 1];
+  const int nb = gridDim.x;
+  for (int c = 0; c < VB_NC; ++c) {
+    if (i < batch) prefix[(int64_t)c * (batch + 1) + i] = sh[c][threadIdx.x] - mine[c];
+    if (threadIdx.x == PLAN_BLOCK - 1) bsum[c * nb + blockIdx.x] = sh[c][PLAN_BLOCK - 1];
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_vb_blocks(int64_t* __restrict__ bsum, int nblocks,
                                                     int64_t* __restrict__ ctrl) {
-  // exclusive scan of bsum in place, 1024 values per pass, carrying the sum
+  // exclusive scan of each class's block sums in place, 1024 per pass
   __shared__ int64_t sh[1024];
   __shared__ int64_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nblocks; base += 1024) {
-    const int i = base + threadIdx.x;
-    const int64_t x = i < nblocks ? bsum[i] : 0;
-    sh[threadIdx.x] = x;
+  for (int c = 0; c < VB_NC; ++c) {
+    int64_t* b = bsum + (int64_t)c * nblocks;
+    if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int64_t y = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    for (int base = 0; base < nblocks; base += 1024) {
+      const int i = base + threadIdx.x;
+      const int64_t x = i < nblocks ? b[i] : 0;
+      sh[threadIdx.x] = x;
       __syncthreads();
-      sh[threadIdx.x] += y;
+      for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t y = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += y;
+        __syncthreads();
+      }
+      if (i < nblocks) b[i] = carry + sh[threadIdx.x] - x;
+      __syncthreads();
+      if (threadIdx.x == 1023) carry += sh[1023];
       __syncthreads();
     }
-    if (i < nblocks) bsum[i] = carry + sh[threadIdx.x] - x;
+    if (threadIdx.x == 0) ctrl[c] = carry;                          // tiles of class c
+    if (threadIdx.x < 8) ctrl[VB_NC + c * 8 + threadIdx.x] = 0;     // its per-XCD heads
     __syncthreads();
-    if (threadIdx.x == 1023) carry += sh[1023];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    ctrl[0] = carry;  // total tiles
-    ctrl[1] = 0;      // queue head
   }
 }
 
@@ -526,25 +633,35 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_vb_finish(int batch, int64_t* __
                                                           const int64_t* __restrict__ ctrl) {
   const int i = blockIdx.x * PLAN_BLOCK + threadIdx.x;
   if (i >= batch) return;
-  prefix[i] += bsum[blockIdx.x];
-  if (i == batch - 1) prefix[batch] = ctrl[0];
+  for (int c = 0; c < VB_NC; ++c) {
+    int64_t* pc = prefix + (int64_t)c * (batch + 1);
+    pc[i] += bsum[c * gridDim.x + blockIdx.x];
+    if (i == batch - 1) pc[batch] = ctrl[c];
+  }
 }
 
-// Writes the tile -> instance map once all prefixes are final.
+// Writes the tile -> instance map (class c's tiles at offset sum_{c'<c} T_c')
+// once all prefixes are final.
 __global__ __launch_bounds__(PLAN_BLOCK) void k_vb_map(int batch, const int64_t* __restrict__ prefix,
                                                        const int64_t* __restrict__ ctrl,
                                                        int* __restrict__ map, int64_t map_cap) {
-  const int64_t total = ctrl[0];
+  int64_t total = 0;
+  for (int c = 0; c < VB_NC; ++c) total += ctrl[c];
   if (total > map_cap) return;
   const int i = blockIdx.x * PLAN_BLOCK + threadIdx.x;
   if (i >= batch) return;
-  const int64_t lo = prefix[i], hi = prefix[i + 1];
-  for (int64_t t = lo; t < hi; ++t) map[t] = i;
+  int64_t moff = 0;
+  for (int c = 0; c < VB_NC; ++c) {
+    const int64_t* pc = prefix + (int64_t)c * (batch + 1);
+    const int64_t lo = pc[i], hi = pc[i + 1];
+    for (int64_t t = lo; t < hi; ++t) map[moff + t] = i;
+    moff += ctrl[c];
+  }
 }
 
-// Instance owning tile q: the last i with prefix[i] <= q (and prefix[i+1] > q).
+// Instance owning tile q of a class: the last i with P[i] <= q < P[i + 1].
 __device__ __forceinline__ int vb_find(const int64_t* __restrict__ prefix, int batch, int64_t q) {
-  int lo = 0, hi = batch;  // invariant: prefix[lo] <= q < prefix[hi]
+  int lo = 0, hi = batch;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (prefix[mid] <= q) lo = mid; else hi = mid;
@@ -552,31 +669,73 @@ __device__ __forceinline__ int vb_find(const int64_t* __restrict__ prefix, int b
   return lo;
 }
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(CfgVb::NT) void k_vb_exec(
+// The tiles of a class are split into eight equal ranges, one per XCD
+// (workgroups reach the XCDs round-robin by id), so that the tiles of an
+// instance run on one XCD and share its L2 for the A and B panels.  A
+// workgroup pops from its own XCD's range first, then steals from the others
+// in turn; every counter is only ever incremented, so each tile is taken
+// exactly once and every workgroup leaves after one pass over the eight.
+template <class CF, bool TA, bool TB>
+__global__ __launch_bounds__(CF::NT) void k_vb_exec(
     const int* __restrict__ m, const int* __restrict__ n, const int* __restrict__ k, double alpha,
     const double* const* __restrict__ Ap, const int* __restrict__ lda,
     const double* const* __restrict__ Bp, const int* __restrict__ ldb, double beta,
-    double* const* __restrict__ Cp, const int* __restrict__ ldc, int batch,
-    const int64_t* __restrict__ prefix, int64_t* __restrict__ ctrl, const int* __restrict__ map,
+    double* const* __restrict__ Cp, const int* __restrict__ ldc, int batch, int cls,
+    const int64_t* __restrict__ prefix_all, int64_t* __restrict__ ctrl, const int* __restrict__ map,
     int64_t map_cap) {
-  __shared__ double lds[SmemMax<CfgVb>::VALUE];
+  __shared__ double lds[Smem<CF, TA, TB>::TOTAL];
   __shared__ int64_t s_q;
-  const int64_t total = ctrl[0];
-  const bool use_map = total <= map_cap;
-  for (;;) {
-    if (threadIdx.x == 0) s_q = atomicAdd((unsigned long long*)&ctrl[1], 1ull);
-    __syncthreads();
-    const int64_t q = s_q;
-    __syncthreads();
-    if (q >= total) break;
-    const int i = use_map ? map[q] : vb_find(prefix, batch, q);
-    const int mi = m[i], ni = n[i], ki = k[i];
-    const int tiles_m = (mi + CfgVb::BM - 1) / CfgVb::BM;
-    const int t = (int)(q - prefix[i]);
-    gemm_tile<CfgVb, TA, TB>(Ap[i], lda[i], Bp[i], ldb[i], Cp[i], ldc[i], mi, ni, ki, alpha, beta,
-                             t % tiles_m, t / tiles_m, (lptr)lds);
+  const int64_t* prefix = prefix_all + (int64_t)cls * (batch + 1);
+  const int64_t total = ctrl[cls];
+  int64_t all = 0, moff = 0;
+  for (int c = 0; c < VB_NC; ++c) {
+    all += ctrl[c];
+    if (c < cls) moff += ctrl[c];
   }
+  const bool use_map = all <= map_cap;
+  unsigned long long* heads = (unsigned long long*)&ctrl[VB_NC + cls * 8];
+  const int home = blockIdx.x % NUM_XCD;
+  for (int step = 0; step < NUM_XCD; ++step) {
+    const int x = (home + step) % NUM_XCD;
+    const int64_t lo = total * x / NUM_XCD, hi = total * (x + 1) / NUM_XCD;
+    for (;;) {
+      if (threadIdx.x == 0) s_q = lo + (int64_t)atomicAdd(&heads[x], 1ull);
+      __syncthreads();
+      const int64_t q = s_q;
+      __syncthreads();
+      if (q >= hi) break;
+      const int i = use_map ? map[moff + q] : vb_find(prefix, batch, q);
+      const int mi = m[i], ni = n[i], ki = k[i];
+      const int tiles_m = (mi + CF::BM - 1) / CF::BM;
+      const int t = (int)(q - prefix[i]);
+      gemm_tile<CF, TA, TB>(Ap[i], lda[i], Bp[i], ldb[i], Cp[i], ldc[i], mi, ni, ki, alpha, beta,
+                            t % tiles_m, t / tiles_m, (lptr)lds);
+      __syncthreads();  // LDS free for the next tile
+    }
+  }
+}
+
+template <class CF, bool TA, bool TB>
+static hipError_t launch_vb_exec(const VbatchedArgs& a, const VbLayout& L, int cls, int num_cus,
+                                 hipStream_t s) {
+  auto kern = k_vb_exec<CF, TA, TB>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, CF::NT, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  hipLaunchKernelGGL(kern, dim3(num_cus * per_cu), dim3(CF::NT), 0, s, a.m, a.n, a.k, a.alpha,
+                     a.A, a.lda, a.B, a.ldb, a.beta, a.C, a.ldc, a.batch, cls, L.prefix, L.ctrl,
+                     L.map, L.map_cap);
+  return hipGetLastError();
+}
+
+template <class CF>
+static hipError_t launch_vb_exec_t(const VbatchedArgs& a, const VbLayout& L, int cls, int num_cus,
+                                   hipStream_t s) {
+  if (!a.ta && !a.tb) return launch_vb_exec<CF, false, false>(a, L, cls, num_cus, s);
+  if (!a.ta && a.tb) return launch_vb_exec<CF, false, true>(a, L, cls, num_cus, s);
+  if (a.ta && !a.tb) return launch_vb_exec<CF, true, false>(a, L, cls, num_cus, s);
+  return launch_vb_exec<CF, true, true>(a, L, cls, num_cus, s);
 }
 
 hipError_t launch_vbatched(const VbatchedArgs& a, const VbWorkspace& ws, int num_cus,
@@ -594,16 +753,9 @@ hipError_t launch_vbatched(const VbatchedArgs& a, const VbWorkspace& ws, int num
                      L.map_cap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-
-  int per_cu = 0;
-  auto kern = a.ta ? (a.tb ? k_vb_exec<true, true> : k_vb_exec<true, false>)
-                   : (a.tb ? k_vb_exec<false, true> : k_vb_exec<false, false>);
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, CfgVb::NT, 0);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  const int grid = num_cus * per_cu;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(CfgVb::NT), 0, s, a.m, a.n, a.k, a.alpha, a.A, a.lda,
-                     a.B, a.ldb, a.beta, a.C, a.ldc, a.batch, L.prefix, L.ctrl, L.map, L.map_cap);
-  return hipGetLastError();
+  if ((e = launch_vb_exec_t<CfgVbL>(a, L, 0, num_cus, s)) != hipSuccess) return e;
+  if ((e = launch_vb_exec_t<CfgVbM>(a, L, 1, num_cus, s)) != hipSuccess) return e;
+  return launch_vb_exec_t<CfgVbS>(a, L, 2, num_cus, s);
 }
 
 }  // namespace bg

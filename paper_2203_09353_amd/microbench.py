@@ -109,4 +109,12 @@ def summary():
 
 
 if __name__ == "__main__":
-    print(json.dumps(summary()))
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "copy":
+        # one warm-up and one timed launch of the copy kernel over N bytes: the
+        # reference dispatch for scaling HBM byte counters
+        nbytes = int(sys.argv[2]) if len(sys.argv) > 2 else 1 << 30
+        gbps, ms = stream_gbps("copy", nbytes=nbytes, reps=1)
+        print(json.dumps({"copy_bytes_each_way": nbytes, "gbps": round(gbps, 1)}))
+    else:
+        print(json.dumps(summary()))

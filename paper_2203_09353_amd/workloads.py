@@ -230,24 +230,28 @@ def host_instance(part, i):
     return tuple(out)
 
 
+PARTS = {
+    "u32": lambda d, b: uniform_part("u32", b(1000), 32, 32, 32, 1.0, 0.0, 0, d, c_nan=True),
+    "u64": lambda d, b: uniform_part("u64", b(200_000), 64, 64, 64, 1.0, 1.0, 1, d),
+    "u256": lambda d, b: uniform_part("u256", b(20_000), 256, 256, 256, 1.0, 1.0, 2, d),
+    "s512": lambda d, b: symmetric_part("s512", b(5_000), 512, 1.0, 1.0, 3, d),
+    "vb": lambda d, b: vb_part("vb", b(100_000), 1.0, 0.5, 4, False, d),
+    "vb8": lambda d, b: vb_part("vb8", b(100_000), 1.0, 0.5, 4, True, d),
+}
+ALIASES = {"config1": "u32", "config2": "u64+u256+s512", "config3": "vb",
+           "config2+vb": "u64+u256+s512+vb"}
+
+
 def build(name: str, device="cuda", scale: float = 1.0):
-    """The parts of a named workload; ``scale`` < 1 shrinks every batch (at
-    least one instance) while keeping the shapes, for tests."""
+    """The parts of a workload: a '+'-joined list of part names (or an alias
+    such as config2+vb).  ``scale`` < 1 shrinks every batch (at least one
+    instance) while keeping the shapes, for tests."""
     b = lambda n: max(1, int(round(n * scale)))
-    parts = []
-    if name == "u32":
-        parts.append(uniform_part("u32", b(1000), 32, 32, 32, 1.0, 0.0, 0, device, c_nan=True))
-    if name in ("config2", "config2+vb"):
-        parts.append(uniform_part("u64", b(200_000), 64, 64, 64, 1.0, 1.0, 1, device))
-        parts.append(uniform_part("u256", b(20_000), 256, 256, 256, 1.0, 1.0, 2, device))
-        parts.append(symmetric_part("s512", b(5_000), 512, 1.0, 1.0, 3, device))
-    if name in ("vb", "config2+vb"):
-        parts.append(vb_part("vb", b(100_000), 1.0, 0.5, 4, False, device))
-    if name == "vb8":
-        parts.append(vb_part("vb8", b(100_000), 1.0, 0.5, 4, True, device))
-    if not parts:
-        raise ValueError("unknown workload " + name)
-    return parts
+    names = ALIASES.get(name, name).split("+")
+    for n in names:
+        if n not in PARTS:
+            raise ValueError("unknown workload part " + n)
+    return [PARTS[n](device, b) for n in names]
 
 
-NAMES = ("u32", "config2", "vb", "vb8", "config2+vb")
+NAMES = tuple(PARTS) + tuple(ALIASES)
