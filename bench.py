@@ -25,6 +25,25 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "hbm_traffic_config2+vb.md")
+
+
+def measured_traffic(part: str, workload: str):
+    """HBM bytes (read + written) per launch of `part` from the committed
+    rocprofv3 counter summary, or None when there is none for this workload or
+    the kernels changed since the counters were taken."""
+    from paper_2203_09353_amd.profile_summary import kernel_source_hash, load_traffic
+    t = load_traffic(TRAFFIC_SUMMARY)
+    if not t or t.get("workload") != workload or t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    p = t["parts"].get(part)
+    if not p:
+        return None
+    return {"bytes": round(p["read_bytes"] + p["write_bytes"]), "read": round(p["read_bytes"]),
+            "written": round(p["write_bytes"]), "source": "profiles/hbm_traffic_config2+vb.md"}
+
+
 def part_launch(h, p):
     from paper_2203_09353_amd.workloads import UniformPart
     if isinstance(p, UniformPart):
@@ -137,7 +156,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="config2+vb")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=3, help="sampled parity instances per part")
     args = ap.parse_args()
@@ -216,7 +235,7 @@ def main():
         roof = {"bound": "hbm", "achieved": round(dp.bytes / sec / 1e9, 1),
                 "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dp.name, args.workload)
     roof["kernel"] = dp.name
 
     cpu = None

@@ -32,8 +32,10 @@ def _hipcc(sources, out, extra=()):
 
 
 def build() -> list[str]:
+    from .tune import cached_defines
+    # tile shapes chosen by the autotuner (tune_cache.json), if any
     outs = [_hipcc([os.path.join(CSRC, "bgemm_api.cpp"), os.path.join(CSRC, "bgemm_kernels.hip")],
-                   LIB)]
+                   LIB, extra=cached_defines(ARCH))]
     mb = os.path.join(CSRC, "microbench.hip")
     if os.path.exists(mb):
         outs.append(_hipcc([mb], MICRO_LIB))

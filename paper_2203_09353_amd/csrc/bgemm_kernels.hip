@@ -55,7 +55,7 @@ typedef const AS_LDS double* lcptr;
 // wave tile WM x WN, SWAP selects the C^T form (P = op(B)^T, Q = op(A)).
 // ---------------------------------------------------------------------------
 template <int BM_, int BN_, int BK_, int WM_, int WN_, bool SWAP_, int NSTAGE_ = 2,
-          bool CPRE_ = false, int SKIP_ = 0>
+          bool CPRE_ = false, int SKIP_ = 0, int PIPE_ = 0>
 struct Cfg {
   static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
   static constexpr bool SWAP = SWAP_;
@@ -64,6 +64,11 @@ struct Cfg {
   // Work skipped on edge tiles: 0 none, 1 waves whose region lies outside C,
   // 2 also single instructions whose 16 x 4 output lies outside C.
   static constexpr int SKIP = SKIP_;
+  // PIPE >= 3: instances whose A and B are 16-byte aligned with even leading
+  // dimensions use the pipelined path, a ring of PIPE LDS stages filled by
+  // direct global-to-LDS loads; 0 disables it.
+  static constexpr int PIPE = PIPE_;
+  static_assert(PIPE == 0 || PIPE >= 3, "the pipelined path needs at least three stages");
   static_assert(NSTAGE == 1 || NSTAGE == 2, "one or two LDS stages");
   static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN;
   static constexpr int NT = WAVES_M * WAVES_N * 64;
@@ -84,7 +89,16 @@ struct Cfg {
 #define BG_CFG64 64, 64, 16, 32, 32, true, 2, true
 #endif
 #ifndef BG_CFG128
-#define BG_CFG128 128, 64, 16, 16, 64, true
+#define BG_CFG128 128, 64, 16, 16, 64, true, 2, false, 0, 3
+#endif
+// Guarded loads as unconditional loads from clamped addresses plus a select
+// (1), or as predicated loads (0).
+#ifndef BG_CLAMPED_LOADS
+#define BG_CLAMPED_LOADS 0
+#endif
+// Epilogue C loads all issued before the stores (1), or per element (0).
+#ifndef BG_EPI_BATCH
+#define BG_EPI_BATCH 1
 #endif
 using Cfg32 = Cfg<BG_CFG32>;
 using Cfg64 = Cfg<BG_CFG64>;
@@ -150,10 +164,20 @@ struct OpLoader {
         const int e = 2 * (tid + it * NT);
         const int cc = e % T::LC, ss = e / T::LC;
         const int c = c0 + cc, s = s0 + ss;
-        gcptr p = base + c + (int64_t)s * ld;
         const bool sok = s < sext;
-        v[it].x = (sok && c < cext) ? p[0] : 0.0;
-        v[it].y = (sok && c + 1 < cext) ? p[1] : 0.0;
+        if (BG_CLAMPED_LOADS) {
+          // unconditional loads from clamped (in-bounds) addresses, then a
+          // select: no branch around each load, so all of them are in flight
+          const int64_t col = (int64_t)(sok ? s : sext - 1) * ld;
+          const double x0 = base[(c < cext ? c : cext - 1) + col];
+          const double x1 = base[(c + 1 < cext ? c + 1 : cext - 1) + col];
+          v[it].x = (sok && c < cext) ? x0 : 0.0;
+          v[it].y = (sok && c + 1 < cext) ? x1 : 0.0;
+        } else {
+          const gcptr p = base + c + (int64_t)s * ld;
+          v[it].x = (sok && c < cext) ? p[0] : 0.0;
+          v[it].y = (sok && c + 1 < cext) ? p[1] : 0.0;
+        }
       }
     }
   }
@@ -207,6 +231,160 @@ __device__ __forceinline__ void read_q(lcptr lds, int mn0, int kk, int tp, int l
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Pipelined path: operand tiles without padding, 16-byte units XOR-swizzled
+// within each row so that the same fragment reads as above stay on distinct
+// banks.  A row is one step of the strided dimension (a column of an
+// MN-contiguous operand, a k-row of a K-contiguous one... in LDS terms: LS rows
+// of UR = LC / 2 units).  Unit u of row r sits at r * UR + (u ^ sw(r)):
+//   K-contiguous  (LC = BK): sw = (r / 2) mod 8 when UR = 8, else r mod 16 --
+//      sixteen rows read at the same unit land in sixteen distinct 16-byte
+//      bank groups;
+//   MN-contiguous (LC = BMN): sw = 8 * ((r / 2) mod 2) -- rows k and k + 2,
+//      read by the two lane groups of a half-wave, fall in opposite halves.
+// A direct load (global_load_lds_dwordx4) writes 64 consecutive units (1 KB)
+// per wave instruction, lane l at unit l; so each lane fetches the global pair
+// that the swizzle places at its unit.
+// ---------------------------------------------------------------------------
+template <int BMN, int BK, bool KC>
+struct SwTile {
+  static constexpr int LC = KC ? BK : BMN;
+  static constexpr int LS = KC ? BMN : BK;
+  static constexpr int UR = LC / 2;
+  static constexpr int UNITS = UR * LS;
+  static constexpr int ELEMS = 2 * UNITS;
+  static_assert((UR & (UR - 1)) == 0 && UR >= 8, "rows of a power-of-two number of units >= 8");
+  static_assert(UNITS % 64 == 0, "whole 1 KB chunks");
+  __device__ __forceinline__ static int sw(int r) {
+    if constexpr (KC) return UR == 8 ? ((r >> 1) & 7) : (r & 15);
+    else return ((r >> 1) & 1) << 3;
+  }
+  // offset (doubles) of logical element (row r, contiguous index c)
+  __device__ __forceinline__ static int off(int r, int c) {
+    return 2 * (r * UR + ((c >> 1) ^ sw(r))) + (c & 1);
+  }
+};
+
+// Issues the direct loads of one operand tile (origin c0 / s0 along the
+// contiguous / strided dims, extents cext / sext; the origin is inside the
+// matrix).  Units outside the matrix read the tile's first pair instead (their
+// products only reach C elements outside the matrix, which are never stored);
+// k beyond K never reaches this path.  A pair straddling an odd cext reads one element of ld padding, which
+// exists because ld is even; the last column, where that could leave the
+// allocation, is always loaded by tail_tile.
+template <class T, int NT>
+__device__ __forceinline__ void dma_tile(gcptr base, int64_t ld, int c0, int s0, int cext,
+                                         int sext, lptr dst, int wave, int lane) {
+  constexpr int NW = NT / 64;
+  constexpr int CH = T::UNITS / 64;
+  static_assert(CH % NW == 0, "chunks not divisible among waves");
+#pragma unroll
+  for (int it = 0; it < CH / NW; ++it) {
+    const int chunk = it * NW + wave;
+    const int unit = chunk * 64 + lane;
+    const int r = unit / T::UR, pu = unit % T::UR;
+    int c = c0 + 2 * (pu ^ T::sw(r));
+    int sr = s0 + r;
+    // Lanes outside the matrix re-read the tile's first pair (in bounds, same
+    // cache lines).  Every wave must issue exactly the same number of direct
+    // loads per step -- the stage waits count them -- so lanes are never
+    // masked off: a wave whose lanes were all masked would skip the
+    // instruction.
+    c = c < cext ? c : c0;
+    sr = sr < sext ? sr : s0;
+    __builtin_amdgcn_global_load_lds((const AS_GLOBAL void*)(base + c + (int64_t)sr * ld),
+                                     (AS_LDS void*)(dst + chunk * 128), 16, 0, 0);
+  }
+}
+
+// Guarded copy of one operand tile through registers, zero outside the
+// matrix; used for the last k-step (partial in k, or holding the last column
+// of an odd-extent MN-contiguous operand).
+template <class T, int NT>
+__device__ __forceinline__ void tail_tile(gcptr base, int64_t ld, int c0, int s0, int cext,
+                                          int sext, lptr dst, int tid) {
+  static_assert(T::UNITS % NT == 0, "whole rounds");
+#pragma unroll
+  for (int e = tid; e < T::UNITS; e += NT) {
+    const int r = e / T::UR, u = e % T::UR;
+    const int c = c0 + 2 * u, sr = s0 + r;
+    const bool ok = sr < sext;
+    d2 v;
+    if (BG_CLAMPED_LOADS) {
+      const int64_t col = (int64_t)(ok ? sr : sext - 1) * ld;
+      const double x0 = base[(c < cext ? c : cext - 1) + col];
+      const double x1 = base[(c + 1 < cext ? c + 1 : cext - 1) + col];
+      v.x = (ok && c < cext) ? x0 : 0.0;
+      v.y = (ok && c + 1 < cext) ? x1 : 0.0;
+    } else {
+      const gcptr p = base + c + (int64_t)sr * ld;
+      v.x = (ok && c < cext) ? p[0] : 0.0;
+      v.y = (ok && c + 1 < cext) ? p[1] : 0.0;
+    }
+    *(AS_LDS d2*)(dst + T::off(r, 2 * u)) = v;
+  }
+}
+
+// Fragment reads from swizzled tiles; same lane / index convention as
+// read_p / read_q.
+template <class T, int NB, bool KC>
+__device__ __forceinline__ void read_p_sw(lcptr lds, int mn0, int kk, int tp, int lane,
+                                          double (&f)[NB][2]) {
+  const int r = lane & 15, s = lane >> 4;
+  const int k = kk + 2 * s + 8 * tp;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if constexpr (KC) {
+      const d2 x = *(const AS_LDS d2*)(lds + T::off(mn0 + 16 * b + r, k));
+      f[b][0] = x.x; f[b][1] = x.y;
+    } else {
+      f[b][0] = lds[T::off(k, mn0 + 16 * b + r)];
+      f[b][1] = lds[T::off(k + 1, mn0 + 16 * b + r)];
+    }
+  }
+}
+
+template <class T, int NG, bool KC>
+__device__ __forceinline__ void read_q_sw(lcptr lds, int mn0, int kk, int tp, int lane,
+                                          double (&f)[NG][2]) {
+  const int j = lane & 3, s = lane >> 4;
+  const int k = kk + 2 * s + 8 * tp;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if constexpr (KC) {
+      const d2 x = *(const AS_LDS d2*)(lds + T::off(mn0 + 4 * g + j, k));
+      f[g][0] = x.x; f[g][1] = x.y;
+    } else {
+      f[g][0] = lds[T::off(k, mn0 + 4 * g + j)];
+      f[g][1] = lds[T::off(k + 1, mn0 + 4 * g + j)];
+    }
+  }
+}
+
+// s_waitcnt immediate: vector-memory count vm, LDS/scalar count lgkm, export
+// count unconstrained (gfx9 encoding).
+constexpr int waitcnt_imm(int vm, int lgkm) {
+  return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | ((lgkm & 15) << 8);
+}
+
+template <class CF, bool TA, bool TB>
+struct PipeSmem {
+  using TAs = SwTile<CF::BM, CF::BK, TA>;
+  using TBs = SwTile<CF::BN, CF::BK, !TB>;
+  static constexpr int STAGE = TAs::ELEMS + TBs::ELEMS;
+  static constexpr int TOTAL = CF::PIPE * STAGE;
+  // direct loads per thread per k-step
+  static constexpr int DPT = (TAs::UNITS + TBs::UNITS) / CF::NT;
+};
+
+// LDS of a kernel that may take either path for a tile
+template <class CF, bool TA, bool TB>
+struct TileSmem {
+  static constexpr int a = Smem<CF, TA, TB>::TOTAL;
+  static constexpr int b = CF::PIPE ? PipeSmem<CF, TA, TB>::TOTAL : 0;
+  static constexpr int TOTAL = a > b ? a : b;
+};
 
 __device__ __forceinline__ bool aligned16(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
@@ -262,12 +440,100 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
 #pragma unroll
       for (int j = 0; j < CF::GQ; ++j) {
         const int row = c_row(i, j), col = c_col(i, j);
-        cpre[CP ? i : 0][CP ? j : 0] =
-            (row < M && col < N) ? C[row + (int64_t)col * ldc] : 0.0;
+        const double x = C[(row < M ? row : M - 1) + (int64_t)(col < N ? col : N - 1) * ldc];
+        cpre[CP ? i : 0][CP ? j : 0] = (row < M && col < N) ? x : 0.0;
       }
   }
 
-  if (use_product) {
+  const bool pipe_ok = CF::PIPE >= 3 && aligned16(A_) && aligned16(B_) && (lda % 2 == 0) &&
+                       (ldb % 2 == 0);
+  if constexpr (CF::PIPE >= 3) {
+    if (use_product && pipe_ok) {
+      using PS = PipeSmem<CF, TA, TB>;
+      using TAs = typename PS::TAs;
+      using TBs = typename PS::TBs;
+      constexpr int NS = CF::PIPE;
+      static_assert(NS <= 5 && 3 * PS::DPT <= 63, "wait counts must fit the vmcnt field");
+      const int a_cext = TA ? K : M, a_sext = TA ? M : K;
+      const int b_cext = TB ? N : K, b_sext = TB ? K : N;
+      const int nk = (K + CF::BK - 1) / CF::BK;
+      // The last k-step goes through registers when it is partial in k, or
+      // when an MN-contiguous operand of odd extent is cut by this tile (its
+      // last column must not be read past its end).
+      const bool a_odd_edge = !TA && (M & 1) && (m0 + CF::BM > M);
+      const bool b_odd_edge = TB && (N & 1) && (n0 + CF::BN > N);
+      const bool last_tail = (K % CF::BK != 0) || a_odd_edge || b_odd_edge;
+      auto issue = [&](int kt, int st) {
+        const lptr la = lds + st * PS::STAGE, lb = la + TAs::ELEMS;
+        const int k0 = kt * CF::BK;
+        if (kt == nk - 1 && last_tail) {
+          if (TA) tail_tile<TAs, CF::NT>(A, lda, k0, m0, a_cext, a_sext, la, tid);
+          else    tail_tile<TAs, CF::NT>(A, lda, m0, k0, a_cext, a_sext, la, tid);
+          if (TB) tail_tile<TBs, CF::NT>(B, ldb, n0, k0, b_cext, b_sext, lb, tid);
+          else    tail_tile<TBs, CF::NT>(B, ldb, k0, n0, b_cext, b_sext, lb, tid);
+        } else {
+          if (TA) dma_tile<TAs, CF::NT>(A, lda, k0, m0, a_cext, a_sext, la, wave, lane);
+          else    dma_tile<TAs, CF::NT>(A, lda, m0, k0, a_cext, a_sext, la, wave, lane);
+          if (TB) dma_tile<TBs, CF::NT>(B, ldb, n0, k0, b_cext, b_sext, lb, wave, lane);
+          else    dma_tile<TBs, CF::NT>(B, ldb, k0, n0, b_cext, b_sext, lb, wave, lane);
+        }
+      };
+#pragma unroll
+      for (int st = 0; st < NS - 1; ++st)
+        if (st < nk) issue(st, st);
+      const int p0 = SW ? wn0 : wm0, q0 = SW ? wm0 : wn0;
+      // Step kt lives in stage kt mod NS.  Its loads are complete once at most
+      // (steps issued after it) x DPT of this wave's loads remain; loads
+      // return in order.  The barrier then publishes every wave's part, and
+      // only after it is the stage read one step earlier refilled.
+      auto step = [&](int kt, auto stage_c) {
+        constexpr int st = decltype(stage_c)::value;
+        const int pending = min(NS - 2, nk - 1 - kt);
+        asm volatile("" ::: "memory");
+        if (pending <= 0) __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
+        else if (pending == 1) __builtin_amdgcn_s_waitcnt(waitcnt_imm(PS::DPT, 0));
+        else if (pending == 2) __builtin_amdgcn_s_waitcnt(waitcnt_imm(2 * PS::DPT, 0));
+        else __builtin_amdgcn_s_waitcnt(waitcnt_imm(3 * PS::DPT, 0));
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kt + NS - 1 < nk) issue(kt + NS - 1, (st + NS - 1) % NS);
+        const lcptr la = lds + st * PS::STAGE, lb = la + TAs::ELEMS;
+        const lcptr lp = SW ? lb : la;
+        const lcptr lq = SW ? la : lb;
+#pragma unroll
+        for (int kk = 0; kk < CF::BK; kk += 16) {
+          if (kt * CF::BK + kk >= K) break;  // whole 16-slices only, as on the other path
+#pragma unroll
+          for (int tp = 0; tp < 2; ++tp) {
+            double fp[CF::FP][2], fq[CF::GQ][2];
+            if constexpr (SW) {
+              read_p_sw<TBs, CF::FP, !TB>(lp, p0, kk, tp, lane, fp);
+              read_q_sw<TAs, CF::GQ, TA>(lq, q0, kk, tp, lane, fq);
+            } else {
+              read_p_sw<TAs, CF::FP, TA>(lp, p0, kk, tp, lane, fp);
+              read_q_sw<TBs, CF::GQ, !TB>(lq, q0, kk, tp, lane, fq);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+              for (int i = 0; i < CF::FP; ++i)
+#pragma unroll
+                for (int j = 0; j < CF::GQ; ++j)
+                  acc[i][j] =
+                      __builtin_amdgcn_mfma_f64_4x4x4f64(fp[i][u], fq[j][u], acc[i][j], 0, 0, 0);
+          }
+        }
+      };
+      for (int kt0 = 0; kt0 < nk; kt0 += NS) {
+        step(kt0, std::integral_constant<int, 0>{});
+        if (kt0 + 1 < nk) step(kt0 + 1, std::integral_constant<int, 1>{});
+        if (kt0 + 2 < nk) step(kt0 + 2, std::integral_constant<int, 2>{});
+        if constexpr (NS > 3) if (kt0 + 3 < nk) step(kt0 + 3, std::integral_constant<int, 3 % NS>{});
+        if constexpr (NS > 4) if (kt0 + 4 < nk) step(kt0 + 4, std::integral_constant<int, 4 % NS>{});
+      }
+    }
+  }
+  if (use_product && !(CF::PIPE >= 3 && pipe_ok)) {
     const lptr la0 = lds, lb0 = lds + CF::NSTAGE * SM::A_ELEMS;
     const int a_cext = TA ? K : M, a_sext = TA ? M : K;
     const int b_cext = TB ? N : K, b_sext = TB ? K : N;
@@ -344,23 +610,50 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
     }
   }
 
-  // Epilogue
+  // Epilogue.  All C loads (beta != 0) are issued first, from clamped
+  // in-bounds addresses, so they are in flight together; the stores are then
+  // predicated on the C bounds (padding rows are never written).
+  double cv[CF::FP][CF::GQ];
+  const bool read_c = BG_EPI_BATCH && beta != 0.0 && !(use_product && prefetch_c);
+  if (read_c) {
+#pragma unroll
+    for (int i = 0; i < CF::FP; ++i)
+#pragma unroll
+      for (int j = 0; j < CF::GQ; ++j) {
+        const int row = c_row(i, j), col = c_col(i, j);
+        cv[i][j] = C[(row < M ? row : M - 1) + (int64_t)(col < N ? col : N - 1) * ldc];
+      }
+  }
 #pragma unroll
   for (int i = 0; i < CF::FP; ++i) {
 #pragma unroll
     for (int j = 0; j < CF::GQ; ++j) {
       const int row = c_row(i, j), col = c_col(i, j);
-      if (row >= M || col >= N) continue;
-      const gptr p = C + row + (int64_t)col * ldc;
-      if (use_product) {
-        double x = alpha * acc[i][j];
-        if (beta != 0.0)
-          x = x + beta * (prefetch_c ? cpre[CP ? i : 0][CP ? j : 0] : *p);
-        *p = x;
-      } else if (beta == 0.0) {
-        *p = 0.0;
-      } else if (beta != 1.0) {
-        *p = beta * (*p);
+      if (BG_EPI_BATCH) {
+        const double c0v = (use_product && prefetch_c) ? cpre[CP ? i : 0][CP ? j : 0] : cv[i][j];
+        double x;
+        if (use_product) {
+          x = alpha * acc[i][j];
+          if (beta != 0.0) x = x + beta * c0v;
+        } else {
+          x = (beta == 0.0) ? 0.0 : beta * c0v;
+        }
+        // beta == 1 without a product leaves C untouched (never reached from
+        // the uniform path, which returns early; a variable-size instance
+        // with k == 0 and beta == 1 has no tiles)
+        if (row < M && col < N && (use_product || beta != 1.0)) C[row + (int64_t)col * ldc] = x;
+      } else {
+        if (row >= M || col >= N) continue;
+        const gptr p = C + row + (int64_t)col * ldc;
+        if (use_product) {
+          double x = alpha * acc[i][j];
+          if (beta != 0.0) x = x + beta * (prefetch_c ? cpre[CP ? i : 0][CP ? j : 0] : *p);
+          *p = x;
+        } else if (beta == 0.0) {
+          *p = 0.0;
+        } else if (beta != 1.0) {
+          *p = beta * (*p);
+        }
       }
     }
   }
@@ -380,7 +673,7 @@ __global__ __launch_bounds__(CF::NT) void k_uniform(
     const double* const* __restrict__ Bp, int64_t ldb, double beta,
     double* const* __restrict__ Cp, int64_t ldc, int tiles_m, int tiles_per_inst,
     int64_t total_tiles, int64_t per_xcd) {
-  __shared__ double lds[Smem<CF, TA, TB>::TOTAL];
+  __shared__ double lds[TileSmem<CF, TA, TB>::TOTAL];
   const int64_t bid = blockIdx.x;
   const int64_t id = (bid % NUM_XCD) * per_xcd + bid / NUM_XCD;
   if (id >= total_tiles) return;
@@ -487,7 +780,7 @@ hipError_t launch_scale(double beta, double* const* C, int64_t ldc, int m, int n
 #endif
 // relative cost per padded C element of the three classes, for the choice
 #ifndef BG_VB_WEIGHTS
-#define BG_VB_WEIGHTS 1.0f, 1.15f, 1.6f
+#define BG_VB_WEIGHTS 1.0f, 1.3f, 2.0f
 #endif
 using CfgVbL = Cfg<BG_CFGVB_L>;
 using CfgVbM = Cfg<BG_CFGVB_M>;
@@ -683,7 +976,7 @@ __global__ __launch_bounds__(CF::NT) void k_vb_exec(
     double* const* __restrict__ Cp, const int* __restrict__ ldc, int batch, int cls,
     const int64_t* __restrict__ prefix_all, int64_t* __restrict__ ctrl, const int* __restrict__ map,
     int64_t map_cap) {
-  __shared__ double lds[Smem<CF, TA, TB>::TOTAL];
+  __shared__ double lds[TileSmem<CF, TA, TB>::TOTAL];
   __shared__ int64_t s_q;
   const int64_t* prefix = prefix_all + (int64_t)cls * (batch + 1);
   const int64_t total = ctrl[cls];

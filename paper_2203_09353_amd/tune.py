@@ -1,0 +1,172 @@
+"""Offline autotuner for the tile classes.
+
+Tile shapes are compile-time template parameters of the HIP kernels (the
+``BG_CFG*`` macros of ``csrc/bgemm_kernels.hip``: BM, BN, BK, WM, WN, C^T form,
+register-path LDS stages, C read up front, edge skipping, pipeline stages).
+The tuner compiles one library per candidate shape of a class, times each on
+that class's workload through the C ABI, and records the winner per
+(GPU architecture, class) in ``tune_cache.json``; ``build.py`` passes the
+cached shapes to hipcc.
+
+    python -m paper_2203_09353_amd.tune build [--out DIR]     # CPU: compile candidates
+    python -m paper_2203_09353_amd.tune run [--out DIR]       # GPU: time them, update the cache
+
+Classes are tuned one at a time with the others at their cached shape.  The
+variable-size classes (L, M, S) share one workload (the 100,000-instance
+batch), since their work interacts through the queues.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tune_cache.json")
+ARCH = os.environ.get("BG_OFFLOAD_ARCH", "gfx950")
+
+# class macro -> (workload parts timed, candidate shapes)
+CANDIDATES = {
+    "BG_CFG64": ("u64", [
+        "64,64,16,32,32,true,2,true,0,3",
+        "64,64,16,32,32,true,2,true,0,4",
+        "64,64,16,32,32,true,2,true,0,0",
+        "64,64,32,32,32,true,2,true,0,3",
+        "64,64,16,64,16,false,2,true,0,3",
+    ]),
+    "BG_CFG128": ("u256+s512", [
+        "128,64,16,16,64,true,2,false,0,3",
+        "128,64,16,16,64,true,2,false,0,4",
+        "128,64,16,16,64,true,2,false,0,0",
+        "128,64,32,16,64,true,2,false,0,3",
+        "128,64,16,32,32,true,2,false,0,3",
+        "64,64,16,16,64,true,2,false,0,3",
+        "128,128,16,32,64,true,2,false,0,3",
+    ]),
+    "BG_CFGVB_L": ("vb", [
+        "128,64,16,32,32,true,2,false,0,3",
+        "128,64,16,16,64,true,2,false,0,3",
+        "128,64,16,32,32,true,2,false,0,0",
+    ]),
+    "BG_CFGVB_M": ("vb", [
+        "64,64,16,32,32,true,2,true,0,3",
+        "64,64,16,32,32,true,2,false,0,3",
+        "64,64,16,32,32,true,2,true,0,0",
+    ]),
+    "BG_CFGVB_S": ("vb", [
+        "32,32,16,32,32,false,2,true,0,3",
+        "32,32,16,32,32,true,2,true,0,3",
+        "32,32,16,32,32,false,2,true,0,0",
+    ]),
+}
+
+
+def load_cache() -> dict:
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def cached_defines(arch: str = ARCH) -> list[str]:
+    """-D definitions for the cached shapes of ``arch`` (empty if none)."""
+    entry = load_cache().get(arch, {})
+    return ["-D%s=%s" % (k, v["shape"]) for k, v in sorted(entry.items()) if "shape" in v]
+
+
+def _variant_name(macro, i):
+    return "%s_%d" % (macro.lower(), i)
+
+
+def cmd_build(out: str):
+    from . import build as b
+    os.makedirs(out, exist_ok=True)
+    base = [d for d in cached_defines()]
+    jobs = []
+    for macro, (_, cands) in CANDIDATES.items():
+        for i, shape in enumerate(cands):
+            defs = [d for d in base if not d.startswith("-D%s=" % macro)] + ["-D%s=%s" % (macro, shape)]
+            jobs.append((os.path.join(out, "libbgemm_%s.so" % _variant_name(macro, i)), defs))
+
+    def one(job):
+        path, defs = job
+        b._hipcc([os.path.join(b.CSRC, "bgemm_api.cpp"), os.path.join(b.CSRC, "bgemm_kernels.hip")],
+                 path, extra=defs)
+        return path
+
+    with ThreadPoolExecutor(max(1, min(8, os.cpu_count() or 1))) as ex:
+        for p in ex.map(one, jobs):
+            print("built", p, flush=True)
+
+
+def _time_parts(lib_path, parts, reps=5):
+    import torch
+    from . import bgemm
+    import bench  # the repository's benchmark driver (launch helpers)
+    bgemm._lib = None
+    bgemm.lib(lib_path)
+    h = bgemm.Handle()
+    total = 0.0
+    for p in parts:
+        for _ in range(2):
+            bench.part_launch(h, p)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            bench.part_launch(h, p)
+        e1.record()
+        torch.cuda.synchronize()
+        total += e0.elapsed_time(e1) / reps
+    h.close()
+    bgemm._lib = None
+    return total
+
+
+def cmd_run(out: str):
+    import torch
+    from . import workloads
+    sys.path.insert(0, os.path.dirname(HERE))
+    cache = load_cache()
+    entry = cache.setdefault(ARCH, {})
+    by_workload = {}
+    for macro, (wl, cands) in CANDIDATES.items():
+        by_workload.setdefault(wl, []).append(macro)
+    for wl, macros in by_workload.items():
+        parts = workloads.build(wl, "cuda")
+        torch.cuda.synchronize()
+        for macro in macros:
+            cands = CANDIDATES[macro][1]
+            times = []
+            for i, shape in enumerate(cands):
+                path = os.path.join(out, "libbgemm_%s.so" % _variant_name(macro, i))
+                ms = _time_parts(path, parts)
+                times.append(ms)
+                print(json.dumps({"class": macro, "shape": shape, "workload": wl, "ms": round(ms, 4)}),
+                      flush=True)
+            best = min(range(len(cands)), key=lambda i: times[i])
+            entry[macro] = {"shape": cands[best], "workload": wl, "ms": round(times[best], 4),
+                            "candidates": {c: round(t, 4) for c, t in zip(cands, times)}}
+        del parts
+        torch.cuda.empty_cache()
+    with open(CACHE, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    print("wrote", CACHE)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("action", choices=["build", "run"])
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "_build", "tune"))
+    a = ap.parse_args()
+    if a.action == "build":
+        cmd_build(a.out)
+    else:
+        cmd_run(a.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -154,3 +154,23 @@ def test_config_1x32_full(h):
     for i in range(batch):
         check_instance(got[i].T, ref[i].T, A.numpy()[i].T, B.numpy()[i].T, np.zeros((m, m)),
                        1.0, 0.0, where="inst %d" % i)
+
+
+@pytest.mark.parametrize("m,n,k", [(65, 63, 17), (129, 131, 33), (127, 5, 255), (7, 9, 13),
+                                   (130, 66, 64), (257, 129, 47)])
+@pytest.mark.parametrize("ta,tb", list(itertools.product("NT", "NT")))
+def test_pipelined_path_odd_extents_even_ld(h, m, n, k, ta, tb):
+    """The 128-tile class loads 16-byte-aligned operands with even leading
+    dimensions through its direct-to-LDS pipeline.  Odd extents with even ld
+    exercise its edge rules: pairs straddling the last row read ld padding,
+    the last column and a partial last k-step go through registers."""
+    def even_pad(rows):
+        return 1 if rows % 2 else 2
+    a_rows = k if ta == "T" else m
+    b_rows = n if tb == "T" else k
+    pads = (even_pad(a_rows), even_pad(b_rows), even_pad(m))
+    run_case(h, ta, tb, m, n, k, 1.0, 0.5, pads=pads, cls=2, batch=3)
+    run_case(h, ta, tb, m, n, k, -2.0, 1.0, pads=pads, cls=2, batch=3, integer=True, seed=7)
+    # tight even ld where the extent is even
+    if a_rows % 2 == 0 and b_rows % 2 == 0 and m % 2 == 0:
+        run_case(h, ta, tb, m, n, k, 1.0, 0.0, pads=(0, 0, 0), cls=2, batch=2)
