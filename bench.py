@@ -1,12 +1,19 @@
 """Benchmark of the batched FP64 GEMM hot path on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload config2+vb]
+    python bench.py --workload config4 [--modes fp64,fp32,bf16,emu3,emu6,emu7]
 
 A step is one pass over every part of the workload: the three uniform
 batches of 64^3, 256^3 and 512^3 (symmetric) instances through
 bg_dgemm_batched and the 100,000-instance variable-size batch through
 bg_dgemm_vbatched (device planning + persistent tile-queue kernel).  Inputs
 are seeded synthetic matrices already resident in HBM.  Prints one JSON line.
+
+``--workload config4`` times the precision modes of bg_gemm_batched_mode on
+20,000 wide-exponent 256^3 instances instead: per mode the time, the
+binary64-equivalent GFLOP/s and the error on sampled instances against the
+binary64 oracle and a compensated (Dot2) reference; ``value`` is the fastest
+mode that reaches binary64 accuracy (relative Frobenius error <= 1e-13).
 """
 from __future__ import annotations
 
@@ -18,6 +25,9 @@ import time
 
 PEAK_FP64 = 78.6e12      # MI355X published FP64 (vector and matrix), flop/s
 PEAK_HBM = 8.0e12        # MI355X published HBM3E bandwidth, bytes/s
+PEAK_FP32_MFMA = 157.3e12  # dense binary32 matrix cores
+PEAK_BF16_MFMA = 2.5e15    # dense bfloat16 matrix cores
+FP64_ACCURACY = 1e-13      # relative Frobenius error that counts as binary64 accuracy
 METRIC = "batched GEMM GFLOP/s at FP64 accuracy, % roofline; p50/p99 request latency"
 
 
@@ -58,6 +68,163 @@ def part_launch(h, p):
                                   p.batch, p.info.data_ptr())
     if st != 0:
         raise RuntimeError("launch of %s failed with status %d" % (p.name, st))
+
+
+def parse_mode(name: str):
+    """'fp64' | 'fp32' | 'bf16' | 'emu<s>' -> (bg_mode_t value, slices)."""
+    fixed = {"fp64": (0, 0), "fp32": (1, 0), "bf16": (2, 0)}
+    if name in fixed:
+        return fixed[name]
+    if name.startswith("emu") and name[3:].isdigit() and 1 <= int(name[3:]) <= 8:
+        return (3, int(name[3:]))
+    raise ValueError("unknown precision mode " + name)
+
+
+def mode_launch(h, p, mode):
+    code, slices = mode
+    pA, pB, pC = p.pointers()
+    st = h.gemm_batched_mode_raw(code, slices, "N", "N", p.m, p.n, p.k, p.alpha, pA.data_ptr(),
+                                 p.A.shape[-1], pB.data_ptr(), p.B.shape[-1], p.beta,
+                                 pC.data_ptr(), p.C.shape[-1], p.batch)
+    if st != 0:
+        raise RuntimeError("mode launch of %s failed with status %d" % (p.name, st))
+
+
+def mode_flops(p, mode):
+    """(binary64-equivalent flops, flops the matrix cores execute) per launch."""
+    f = p.flops
+    code, s = mode
+    return f, (f * s * (s + 1) / 2 if code == 3 else f)
+
+
+def mode_peak(mode):
+    return {0: PEAK_FP64, 1: PEAK_FP32_MFMA, 2: PEAK_BF16_MFMA, 3: PEAK_BF16_MFMA}[mode[0]]
+
+
+def precision_bench(args, h, parts):
+    """The config4 line: every mode in --modes on the wide-exponent batch."""
+    import numpy as np
+    import torch
+    import oracle
+    from oracle import precision as P
+    from paper_2203_09353_amd import inputs
+    from paper_2203_09353_amd.workloads import host_instance
+
+    p = parts[0]
+    names = args.modes.split(",")
+    modes = [parse_mode(n) for n in names]
+    idx = inputs.permutation(11, 4, p.batch)[:max(1, args.check)].tolist()
+    picks = []
+    for i in idx:
+        A, B, _ = host_instance(p, i)
+        Am, Bm = np.ascontiguousarray(A[:, :p.m].T), np.ascontiguousarray(B[:, :p.k].T)
+        C = np.zeros((p.n, p.m))
+        oracle.gemm("N", "N", p.m, p.n, p.k, 1.0, A, A.shape[-1], B, B.shape[-1], 0.0, C, p.m)
+        picks.append((i, Am, Bm, C.T.copy(), P.dot2_gemm(Am, Bm), np.abs(Am) @ np.abs(Bm)))
+    log("references for %d sampled instances ready" % len(picks))
+    oracle_floor = max(P.relative_errors(f64, d2)[0] for _, _, _, f64, d2, _ in picks)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for name, mode in zip(names, modes):
+        p.C.fill_(float("nan"))
+        mode_launch(h, p, mode)
+        torch.cuda.synchronize()
+        fro, fro64, comp, exact = [], [], [], None
+        for j, (i, Am, Bm, f64, d2, mag) in enumerate(picks):
+            G = np.ascontiguousarray(p.C[i].cpu().numpy()[:, :p.m].T)
+            fro.append(P.relative_errors(G, d2)[0])
+            fro64.append(P.relative_errors(G, f64)[0])
+            comp.append(float(np.max(np.abs(G - d2) / np.where(mag > 0, mag, 1.0))))
+            if mode[0] == 3 and j == 0:
+                ref = P.emulated_gemm(Am, Bm, mode[1])
+                exact = bool(np.array_equal(G.view(np.int64), ref.view(np.int64)))
+        for _ in range(args.warmup):
+            mode_launch(h, p, mode)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record(stream)
+            mode_launch(h, p, mode)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+        f64_flops, core_flops = mode_flops(p, mode)
+        row = {"mode": name, "ms": round(ms, 4), "wall_ms": round(wall * 1e3, 4),
+               "gflops_fp64_equiv": round(f64_flops / (ms * 1e-3) / 1e9, 1),
+               "core_tflops": round(core_flops / (ms * 1e-3) / 1e12, 2),
+               "core_peak_frac": round(core_flops / (ms * 1e-3) / mode_peak(mode), 4),
+               "max_rel_fro_vs_dot2": float("%.3e" % max(fro)),
+               "mean_rel_fro_vs_dot2": float("%.3e" % (sum(fro) / len(fro))),
+               "max_rel_fro_vs_fp64_oracle": float("%.3e" % max(fro64)),
+               "max_componentwise_vs_dot2": float("%.3e" % max(comp)),
+               "fp64_accuracy": bool(max(fro) <= FP64_ACCURACY)}
+        if exact is not None:
+            row["bit_exact_vs_oracle"] = exact
+        log(json.dumps(row))
+        rows.append(row)
+    ok = [r for r in rows if r["fp64_accuracy"]]
+    best = max(ok or rows, key=lambda r: r["gflops_fp64_equiv"])
+    bmode = parse_mode(best["mode"])
+    sec = best["ms"] * 1e-3
+    core = mode_flops(p, bmode)[1]
+    roof = {"bound": "mfma", "achieved": round(core / sec / 1e12, 3),
+            "peak": mode_peak(bmode) / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = None
+    roof["kernel"] = "%s (%s)" % (p.name, best["mode"])
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle of mode %s on a sample" % best["mode"])
+        cpu = precision_cpu_baseline(p, bmode, args.cpu_seconds)
+    dtype = {0: "f64", 1: "f32", 2: "bf16", 3: "bf16 slices (f32 sums, f64 recombination)"}[bmode[0]]
+    out = {"metric": METRIC, "value": best["gflops_fp64_equiv"], "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic (seeded counter-based s m 2^e, m in [1,2), e in -20..20)",
+           "config": {"workload": "config4", "parts": "%s x%d" % (p.name, p.batch),
+                      "mode": best["mode"],
+                      "accuracy_rule": "max rel Frobenius vs Dot2 <= %g" % FP64_ACCURACY},
+           "roofline": roof, "cpu_baseline": cpu, "modes": rows,
+           "fp64_oracle_floor_vs_dot2": float("%.3e" % oracle_floor)}
+    print(json.dumps(out), flush=True)
+
+
+def precision_cpu_baseline(p, mode, seconds):
+    """The oracle of `mode` (binary64 C oracle or the precision oracle) on the
+    first instances of the part, for about `seconds` of work."""
+    import numpy as np
+    import oracle
+    from oracle import precision as P
+    from paper_2203_09353_amd.workloads import host_instance
+
+    threads = len(os.sched_getaffinity(0))
+    t, n = 0.0, 0
+    used = 1
+    while t < seconds and n < p.batch:
+        A, B, _ = host_instance(p, n)
+        if mode[0] == 0:
+            C = np.zeros((p.n, p.m))
+            t0 = time.perf_counter()
+            oracle.gemm("N", "N", p.m, p.n, p.k, 1.0, A, A.shape[-1], B, B.shape[-1], 0.0, C, p.m)
+            t += time.perf_counter() - t0
+        else:
+            Am, Bm = np.ascontiguousarray(A[:, :p.m].T), np.ascontiguousarray(B[:, :p.k].T)
+            t0 = time.perf_counter()
+            if mode[0] == 3:
+                P.emulated_gemm(Am, Bm, mode[1])
+            else:
+                P.reference_product(Am, Bm, "fp32" if mode[0] == 1 else "bf16")
+                used = threads
+            t += time.perf_counter() - t0
+        n += 1
+    flops = 2.0 * p.m * p.n * p.k * n
+    return {"value": round(flops / t / 1e9, 3), "unit": "GFLOP/s", "cores": used,
+            "kind": "oracle",
+            "sample": "first %d of %d instances of %s, one at a time, %.1f s" % (
+                n, p.batch, p.name, t)}
 
 
 def sampled_parity(h, parts, per_part, seed=11):
@@ -159,6 +326,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=3, help="sampled parity instances per part")
+    ap.add_argument("--modes", default="fp64,fp32,bf16,emu3,emu6,emu7",
+                    help="precision modes timed by --workload config4")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -182,6 +351,10 @@ def main():
     torch.cuda.synchronize()
     log("built in %.1f s; device memory %.1f GB" % (time.perf_counter() - t0,
                                                      torch.cuda.memory_allocated() / 1e9))
+
+    if args.workload == "config4":
+        precision_bench(args, h, parts)
+        return
 
     parity = sampled_parity(h, parts, args.check) if args.check > 0 else {}
     log("sampled parity (max rel Frobenius per part): %s" % parity)

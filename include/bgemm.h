@@ -127,6 +127,44 @@ bg_status_t bg_dgemm_vbatched(bg_handle_t h, char transa, char transb,
                               double* const* dC, const int* d_ldc,
                               int batch, int* d_info);
 
+/* Arithmetic of bg_gemm_batched_mode.  Inputs and outputs stay binary64; only
+ * the arithmetic inside the product changes:
+ *   BG_MODE_FP64  the binary64 path of bg_dgemm_batched (slices ignored);
+ *   BG_MODE_FP32  A and B rounded to binary32 (nearest even), products summed
+ *                 in binary32 on the matrix cores;
+ *   BG_MODE_BF16  A and B rounded to binary32 and then to bfloat16 (nearest
+ *                 even at each step), products summed in binary32;
+ *   BG_MODE_EMU   binary64 emulated with `slices` (1..8) bfloat16 digit slices
+ *                 per operand: per 32-wide chunk of k each row of A and column
+ *                 of B is scaled by a power of two into (-1, 1) and cut into
+ *                 8-bit signed digits; the digit products up to the
+ *                 (slices + 1)-th diagonal are summed exactly in binary32 and
+ *                 recombined in binary64 in a fixed order, so every result is
+ *                 reproducible bit for bit.  The error falls by about 2^-8 per
+ *                 added slice; 7 slices reach the binary64 path's accuracy on
+ *                 well-scaled data.
+ * The paper computes in binary64 only (Section II); these modes are an
+ * extension for callers that trade accuracy for matrix-core throughput. */
+typedef enum {
+  BG_MODE_FP64 = 0,
+  BG_MODE_FP32 = 1,
+  BG_MODE_BF16 = 2,
+  BG_MODE_EMU = 3
+} bg_mode_t;
+
+/* Uniform batch as bg_dgemm_batched, computed in `mode`.  Arguments, layout,
+ * ownership, quick returns and the alpha/beta rules are those of
+ * bg_dgemm_batched (alpha == 0 or k == 0 gives C <- beta * C in binary64 for
+ * every mode).  The reduced modes take non-transposed operands only
+ * (transa == transb == 'N'); a transposed operand with such a mode returns
+ * BG_STATUS_NOT_SUPPORTED.  A bad mode records argument number 101, a slice
+ * count outside 1..8 for BG_MODE_EMU records 102 (both INVALID_VALUE). */
+bg_status_t bg_gemm_batched_mode(bg_handle_t h, int mode, int slices, char transa, char transb,
+                                 int m, int n, int k, double alpha,
+                                 const double* const* dA, int lda,
+                                 const double* const* dB, int ldb, double beta,
+                                 double* const* dC, int ldc, int batch);
+
 /* Overrides the size class chosen for uniform batches (-1 = automatic;
  * 0 = 32x32 tiles, 1 = 64x64, 2 = 128x128).  For tuning and tests. */
 bg_status_t bg_set_uniform_class(bg_handle_t h, int cls);

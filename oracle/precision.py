@@ -42,6 +42,15 @@ Modes
   Since every rounding is fixed in kind and order, a device implementing
   these steps must match this oracle bit for bit.
 
+Error reference
+---------------
+``dot2_gemm`` is the compensated product of Ogita, Rump and Oishi ("Accurate
+sum and dot product", SIAM J. Sci. Comput. 26(6), 2005, algorithm Dot2):
+each entry is computed as if in twice binary64 precision and then rounded, so
+the error of the binary64 oracle itself becomes visible beside a mode's error.
+Error-free transformations: TwoSum (Knuth) and TwoProduct (Dekker, with
+Veltkamp's split by 2^27 + 1; valid while |entries| stay below about 2^995).
+
 Parity status: every function is pinned in tests/test_oracle_precision.py.
 """
 from __future__ import annotations
@@ -119,6 +128,41 @@ def emulated_gemm(A, B, s, alpha=1.0, beta=0.0, C0=None):
     if beta == 0.0:
         return alpha * acc
     return alpha * acc + beta * np.asarray(C0, dtype=np.float64)
+
+
+def _two_sum(a, b):
+    s = a + b
+    z = s - a
+    return s, (a - (s - z)) + (b - z)
+
+
+def _split(a):
+    c = 134217729.0 * a          # 2^27 + 1
+    hi = c - (c - a)
+    return hi, a - hi
+
+
+def _two_product(a, b):
+    p = a * b
+    ah, al = _split(a)
+    bh, bl = _split(b)
+    return p, al * bl - (((p - ah * bh) - al * bh) - ah * bl)
+
+
+def dot2_gemm(A, B):
+    """A B with every entry from Dot2 over p ascending (binary64 result)."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    m, k = A.shape
+    n = B.shape[1]
+    if k == 0:
+        return np.zeros((m, n))
+    p, s = _two_product(A[:, :1], B[:1, :])
+    for q in range(1, k):
+        h, r = _two_product(A[:, q:q + 1], B[q:q + 1, :])
+        p, e = _two_sum(p, h)
+        s = s + (e + r)
+    return p + s
 
 
 def relative_errors(C, ref):

@@ -27,7 +27,11 @@ STATUS = {0: "SUCCESS", 1: "INVALID_VALUE", 2: "NOT_SUPPORTED", 3: "DEVICE_ERROR
 EXPORTS = ["bg_version", "bg_status_string", "bg_create", "bg_destroy", "bg_set_stream",
            "bg_get_stream", "bg_set_workspace", "bg_workspace_bytes_needed",
            "bg_last_invalid_arg", "bg_check_batched_args", "bg_dgemm_batched",
-           "bg_dgemm_vbatched", "bg_set_uniform_class"]
+           "bg_dgemm_vbatched", "bg_set_uniform_class", "bg_gemm_batched_mode"]
+
+# bg_mode_t
+MODE_FP64, MODE_FP32, MODE_BF16, MODE_EMU = 0, 1, 2, 3
+MODES = {"fp64": MODE_FP64, "fp32": MODE_FP32, "bf16": MODE_BF16, "emu": MODE_EMU}
 
 
 class BgemmError(RuntimeError):
@@ -78,6 +82,8 @@ def lib(path: str | None = None):
     L.bg_dgemm_vbatched.argtypes = [vp, c, c, vp, vp, vp, d, vp, vp, vp, vp, d, vp, vp, i, vp]
     L.bg_set_uniform_class.restype = i
     L.bg_set_uniform_class.argtypes = [vp, i]
+    L.bg_gemm_batched_mode.restype = i
+    L.bg_gemm_batched_mode.argtypes = [vp, i, i, c, c, i, i, i, d, vp, i, vp, i, d, vp, i, i]
     _lib = L
     return L
 
@@ -154,6 +160,13 @@ class Handle:
         return self._L.bg_dgemm_batched(self._h, _ch(transa), _ch(transb), m, n, k, float(alpha),
                                         pA, lda, pB, ldb, float(beta), pC, ldc, batch)
 
+    def gemm_batched_mode_raw(self, mode, slices, transa, transb, m, n, k, alpha, pA, lda, pB,
+                              ldb, beta, pC, ldc, batch) -> int:
+        self._sync_stream()
+        return self._L.bg_gemm_batched_mode(self._h, int(mode), int(slices), _ch(transa),
+                                            _ch(transb), m, n, k, float(alpha), pA, lda, pB, ldb,
+                                            float(beta), pC, ldc, batch)
+
     def dgemm_vbatched_raw(self, transa, transb, pm, pn, pk, alpha, pA, plda, pB, pldb, beta, pC,
                            pldc, batch, pinfo) -> int:
         self._sync_stream()
@@ -178,6 +191,27 @@ class Handle:
                                     pB.data_ptr(), ldb, beta, pC.data_ptr(), ldc, batch)
         if st != 0:
             raise BgemmError("bg_dgemm_batched", st, self.last_invalid_arg())
+        return ptrs
+
+    def batched_mode(self, mode, A, B, C, m, n, k, alpha=1.0, beta=0.0, slices=0, transa="N",
+                     transb="N", ptrs=None):
+        """As ``batched`` in precision mode ``mode`` ("fp64", "fp32", "bf16",
+        "emu" or a bg_mode_t value); ``slices`` is the emulated mode's digit
+        slice count (1..8)."""
+        mode = MODES.get(mode, mode) if isinstance(mode, str) else mode
+        if isinstance(mode, str):
+            raise ValueError("unknown mode " + mode)
+        a0, b0, c0 = A[0], B[0], C[0]
+        lda, ldb, ldc = a0.shape[-1], b0.shape[-1], c0.shape[-1]
+        batch = C.shape[0] if isinstance(C, torch.Tensor) else len(C)
+        if ptrs is None:
+            ptrs = (pointer_array(A), pointer_array(B), pointer_array(C))
+        pA, pB, pC = ptrs
+        st = self.gemm_batched_mode_raw(mode, slices, transa, transb, m, n, k, alpha,
+                                        pA.data_ptr(), lda, pB.data_ptr(), ldb, beta,
+                                        pC.data_ptr(), ldc, batch)
+        if st != 0:
+            raise BgemmError("bg_gemm_batched_mode", st, self.last_invalid_arg())
         return ptrs
 
     def vbatched(self, As, Bs, Cs, ms, ns, ks, alpha=1.0, beta=0.0, transa="N", transb="N",

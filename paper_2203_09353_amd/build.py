@@ -13,6 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbgemm.so")
 MICRO_LIB = os.path.join(HERE, "libbgemm_microbench.so")
 ARCH = os.environ.get("BG_OFFLOAD_ARCH", "gfx950")
+SOURCES = [os.path.join(CSRC, f) for f in ("bgemm_api.cpp", "bgemm_kernels.hip", "bgemm_lowp.hip")]
 
 # Packed FP32 instructions are kept out of every device build.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -34,8 +35,7 @@ def _hipcc(sources, out, extra=()):
 def build() -> list[str]:
     from .tune import cached_defines
     # tile shapes chosen by the autotuner (tune_cache.json), if any
-    outs = [_hipcc([os.path.join(CSRC, "bgemm_api.cpp"), os.path.join(CSRC, "bgemm_kernels.hip")],
-                   LIB, extra=cached_defines(ARCH))]
+    outs = [_hipcc(SOURCES, LIB, extra=cached_defines(ARCH))]
     mb = os.path.join(CSRC, "microbench.hip")
     if os.path.exists(mb):
         outs.append(_hipcc([mb], MICRO_LIB))

@@ -98,7 +98,7 @@ bg_status_t bg_create(bg_handle_t* out) {
 bg_status_t bg_destroy(bg_handle_t h) {
   if (!valid(h)) return BG_STATUS_INVALID_HANDLE;
   hipError_t e = hipStreamSynchronize(h->stream);
-  if (h->ws) hipFree(h->ws);
+  if (h->ws) (void)hipFree(h->ws);
   h->magic = 0;
   free(h);
   return e == hipSuccess ? BG_STATUS_SUCCESS : BG_STATUS_DEVICE_ERROR;
@@ -127,7 +127,7 @@ bg_status_t bg_set_workspace(bg_handle_t h, unsigned long long bytes) {
   if (hipStreamSynchronize(h->stream) != hipSuccess) return BG_STATUS_DEVICE_ERROR;
   void* p = nullptr;
   if (hipMalloc(&p, (size_t)bytes) != hipSuccess) return BG_STATUS_ALLOC_FAILED;
-  if (h->ws) hipFree(h->ws);
+  if (h->ws) (void)hipFree(h->ws);
   h->ws = p;
   h->ws_bytes = (size_t)bytes;
   return BG_STATUS_SUCCESS;
@@ -191,6 +191,43 @@ bg_status_t bg_dgemm_batched(bg_handle_t h, char transa, char transb, int m, int
     a.batch = batch;
     const bg::TileClass cls = bg::pick_uniform_class(m, n, k, h->force_class);
     e = bg::launch_uniform(a, cls, h->stream);
+    if (e == hipErrorInvalidValue) return BG_STATUS_NOT_SUPPORTED;
+  }
+  return e == hipSuccess ? BG_STATUS_SUCCESS : BG_STATUS_DEVICE_ERROR;
+}
+
+bg_status_t bg_gemm_batched_mode(bg_handle_t h, int mode, int slices, char transa, char transb,
+                                 int m, int n, int k, double alpha, const double* const* dA,
+                                 int lda, const double* const* dB, int ldb, double beta,
+                                 double* const* dC, int ldc, int batch) {
+  if (!valid(h)) return BG_STATUS_INVALID_HANDLE;
+  if (mode == BG_MODE_FP64)
+    return bg_dgemm_batched(h, transa, transb, m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc,
+                            batch);
+  int bad = 0;
+  if (mode != BG_MODE_FP32 && mode != BG_MODE_BF16 && mode != BG_MODE_EMU) bad = 101;
+  else if (mode == BG_MODE_EMU && (slices < 1 || slices > 8)) bad = 102;
+  else bad = bg_check_batched_args(transa, transb, m, n, k, dA, lda, dB, ldb, dC, ldc, batch);
+  h->last_invalid_arg = bad;
+  if (bad) return BG_STATUS_INVALID_VALUE;
+  if (batch == 0 || m == 0 || n == 0) return BG_STATUS_SUCCESS;
+  const bool no_product = (alpha == 0.0 || k == 0);
+  if (no_product && beta == 1.0) return BG_STATUS_SUCCESS;
+  if (!no_product && (trans_code(transa) != 0 || trans_code(transb) != 0))
+    return BG_STATUS_NOT_SUPPORTED;
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return BG_STATUS_DEVICE_ERROR;
+  hipError_t e;
+  if (no_product) {
+    e = bg::launch_scale(beta, dC, ldc, m, n, batch, h->stream);
+  } else {
+    bg::UniformArgs a;
+    a.ta = false; a.tb = false;
+    a.m = m; a.n = n; a.k = k;
+    a.alpha = alpha; a.beta = beta;
+    a.A = dA; a.lda = lda; a.B = dB; a.ldb = ldb; a.C = dC; a.ldc = ldc;
+    a.batch = batch;
+    e = bg::launch_uniform_lowp(a, mode, slices, h->stream);
     if (e == hipErrorInvalidValue) return BG_STATUS_NOT_SUPPORTED;
   }
   return e == hipSuccess ? BG_STATUS_SUCCESS : BG_STATUS_DEVICE_ERROR;

@@ -36,6 +36,11 @@ struct UniformArgs {
 // Launches the uniform batched GEMM (product path; alpha != 0, k > 0).
 hipError_t launch_uniform(const UniformArgs& a, TileClass cls, hipStream_t s);
 
+// Reduced / emulated precision modes of the uniform batch (NN operands only):
+// mode 1 binary32, 2 bfloat16, 3 emulated binary64 with `slices` (1..8)
+// bfloat16 digit slices.  hipErrorInvalidValue for grids beyond int32.
+hipError_t launch_uniform_lowp(const UniformArgs& a, int mode, int slices, hipStream_t s);
+
 // Launches C_i <- beta * C_i (beta != 1) for every instance, used when the
 // product term vanishes (alpha == 0 or k == 0).
 hipError_t launch_scale(double beta, double* const* C, int64_t ldc, int m, int n, int batch,

@@ -6,6 +6,8 @@
 #include <stdint.h>
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // One v_mfma_f64_16x16x4_f64 by one wave: a[64], b[64] are the per-lane
 // source values, c[4*64] the per-lane accumulator (register v of lane l at
@@ -23,6 +25,30 @@ template <int CBSZ, int ABID>
 __global__ void k_mfma4_once(const double* a, const double* b, const double* c, double* d) {
   const int l = threadIdx.x;
   d[l] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[l], b[l], c[l], CBSZ, ABID, 0);
+}
+
+// One v_mfma_f32_16x16x4_f32: a[64], b[64] per-lane floats, c/d[4*64].
+__global__ void k_mfma_f32_once(const float* a, const float* b, const float* c, float* d) {
+  const int l = threadIdx.x;
+  f4 acc = {c[4 * l], c[4 * l + 1], c[4 * l + 2], c[4 * l + 3]};
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[l], b[l], acc, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) d[4 * l + v] = acc[v];
+}
+
+// One v_mfma_f32_16x16x32_bf16: a/b[8*64] per-lane bfloat16 bit patterns
+// (element e of lane l at 8*l + e), c/d[4*64] floats.
+__global__ void k_mfma_bf16_once(const unsigned short* a, const unsigned short* b, const float* c,
+                                 float* d) {
+  const int l = threadIdx.x;
+  bf8 va, vb;
+  for (int e = 0; e < 8; ++e) {
+    unsigned short xa = a[8 * l + e], xb = b[8 * l + e];
+    va[e] = __builtin_bit_cast(__bf16, xa);
+    vb[e] = __builtin_bit_cast(__bf16, xb);
+  }
+  f4 acc = {c[4 * l], c[4 * l + 1], c[4 * l + 2], c[4 * l + 3]};
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, acc, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) d[4 * l + v] = acc[v];
 }
 
 // CHAINS independent accumulators per wave, `iters` rounds of CHAINS MFMAs.
@@ -129,6 +155,17 @@ extern "C" {
 
 int mb_mfma_f64_16x16x4(const double* a, const double* b, const double* c, double* d) {
   hipLaunchKernelGGL(k_mfma_once, dim3(1), dim3(64), 0, 0, a, b, c, d);
+  return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
+}
+
+int mb_mfma_f32_16x16x4(const float* a, const float* b, const float* c, float* d) {
+  hipLaunchKernelGGL(k_mfma_f32_once, dim3(1), dim3(64), 0, 0, a, b, c, d);
+  return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
+}
+
+int mb_mfma_bf16_16x16x32(const unsigned short* a, const unsigned short* b, const float* c,
+                          float* d) {
+  hipLaunchKernelGGL(k_mfma_bf16_once, dim3(1), dim3(64), 0, 0, a, b, c, d);
   return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
 }
 

@@ -162,6 +162,18 @@ def log_uniform_sizes(seed: int, stream: int, count: int, jmin=3, jmax=9):
     return (2 ** j) + dlt
 
 
+def wide_flat(seed: int, stream: int, start: int, count: int, emax: int = 20,
+              device="cpu") -> torch.Tensor:
+    """Values s * m * 2**e with m uniform in [1, 2), s = +-1 equiprobable and
+    e uniform on the integers -emax..emax (two streams: 2 * stream gives s
+    and m, 2 * stream + 1 gives e)."""
+    v = uniform_flat(seed, 2 * stream, start, count, device)
+    w = uniform_flat(seed, 2 * stream + 1, start, count, device)
+    e = torch.clamp(((w + 1.0) * 0.5 * (2 * emax + 1)).floor(), 0, 2 * emax) - emax
+    mag = 1.0 + torch.abs(v)
+    return torch.where(v < 0, -mag, mag) * torch.exp2(e)
+
+
 def permutation(seed: int, stream: int, count: int) -> torch.Tensor:
     """A seeded permutation of range(count) (argsort of uniform keys)."""
     return torch.argsort(uniform_flat(seed, stream, 0, count), stable=True)

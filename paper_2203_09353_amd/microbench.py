@@ -25,6 +25,10 @@ def lib():
         vp = ctypes.c_void_p
         L.mb_mfma_f64_16x16x4.restype = ctypes.c_int
         L.mb_mfma_f64_16x16x4.argtypes = [vp, vp, vp, vp]
+        L.mb_mfma_f32_16x16x4.restype = ctypes.c_int
+        L.mb_mfma_f32_16x16x4.argtypes = [vp, vp, vp, vp]
+        L.mb_mfma_bf16_16x16x32.restype = ctypes.c_int
+        L.mb_mfma_bf16_16x16x32.argtypes = [vp, vp, vp, vp]
         L.mb_mfma_f64_4x4x4.restype = ctypes.c_int
         L.mb_mfma_f64_4x4x4.argtypes = [vp, vp, vp, vp, ctypes.c_int]
         L.mb_fp64_peak_ms.restype = ctypes.c_double
@@ -58,6 +62,31 @@ def mfma4_once(a, b, c, mode=0):
     torch.cuda.synchronize()
     assert lib().mb_mfma_f64_4x4x4(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(),
                                    d.data_ptr(), int(mode)) == 0
+    return d.cpu()
+
+
+def mfma_f32_once(a, b, c):
+    """One v_mfma_f32_16x16x4_f32: a, b (64,) floats, c (64, 4).  Returns (64, 4)."""
+    dev = torch.device("cuda")
+    t = [torch.as_tensor(x, dtype=torch.float32).to(dev).contiguous() for x in (a, b, c)]
+    d = torch.empty(64, 4, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    assert lib().mb_mfma_f32_16x16x4(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(),
+                                     d.data_ptr()) == 0
+    return d.cpu()
+
+
+def mfma_bf16_once(a, b, c):
+    """One v_mfma_f32_16x16x32_bf16: a, b (64, 8) values (rounded to bfloat16
+    here), c (64, 4) floats.  Returns (64, 4) floats."""
+    dev = torch.device("cuda")
+    ab = [torch.as_tensor(x, dtype=torch.float32).to(torch.bfloat16).view(torch.int16).to(dev)
+          .contiguous() for x in (a, b)]
+    ct = torch.as_tensor(c, dtype=torch.float32).to(dev).contiguous()
+    d = torch.empty(64, 4, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    assert lib().mb_mfma_bf16_16x16x32(ab[0].data_ptr(), ab[1].data_ptr(), ct.data_ptr(),
+                                       d.data_ptr()) == 0
     return d.cpu()
 
 

@@ -31,35 +31,43 @@ ARCH = os.environ.get("BG_OFFLOAD_ARCH", "gfx950")
 # class macro -> (workload parts timed, candidate shapes)
 CANDIDATES = {
     "BG_CFG64": ("u64", [
+        "64,64,16,32,32,true,2,true",
         "64,64,16,32,32,true,2,true,0,3",
-        "64,64,16,32,32,true,2,true,0,4",
-        "64,64,16,32,32,true,2,true,0,0",
-        "64,64,32,32,32,true,2,true,0,3",
-        "64,64,16,64,16,false,2,true,0,3",
+        "64,64,32,32,32,true,2,true",
+        "64,64,16,64,16,false,2,true",
+        "64,64,16,32,32,true,2,false",
     ]),
     "BG_CFG128": ("u256+s512", [
         "128,64,16,16,64,true,2,false,0,3",
-        "128,64,16,16,64,true,2,false,0,4",
-        "128,64,16,16,64,true,2,false,0,0",
+        "128,64,16,16,64,true,2,true,0,3",
+        "128,64,16,16,64,true",
+        "128,64,16,16,64,true,2,true",
         "128,64,32,16,64,true,2,false,0,3",
-        "128,64,16,32,32,true,2,false,0,3",
+        "128,64,32,16,64,true,2,true,0,3",
         "64,64,16,16,64,true,2,false,0,3",
-        "128,128,16,32,64,true,2,false,0,3",
     ]),
     "BG_CFGVB_L": ("vb", [
-        "128,64,16,32,32,true,2,false,0,3",
+        "128,64,16,32,32,true",
+        "128,64,16,16,64,true",
         "128,64,16,16,64,true,2,false,0,3",
-        "128,64,16,32,32,true,2,false,0,0",
+        "128,64,16,32,32,true,2,true",
+        "64,128,16,32,32,true",
+        "128,64,16,32,32,true,2,false,0,3",
     ]),
     "BG_CFGVB_M": ("vb", [
+        "64,64,16,32,32,true,2,true",
+        "64,64,32,32,32,true,2,true",
+        "64,64,16,32,32,true",
+        "64,64,16,64,16,false,2,true",
         "64,64,16,32,32,true,2,true,0,3",
-        "64,64,16,32,32,true,2,false,0,3",
-        "64,64,16,32,32,true,2,true,0,0",
     ]),
     "BG_CFGVB_S": ("vb", [
+        "32,32,16,32,32,false,2,true",
+        "32,32,16,32,32,true,2,true",
+        "32,32,16,32,32,false",
+        "32,32,16,16,32,false,2,true",
         "32,32,16,32,32,false,2,true,0,3",
-        "32,32,16,32,32,true,2,true,0,3",
-        "32,32,16,32,32,false,2,true,0,0",
+        "32,32,16,32,32,true,2,true,0,4",
     ]),
 }
 
@@ -93,8 +101,7 @@ def cmd_build(out: str):
 
     def one(job):
         path, defs = job
-        b._hipcc([os.path.join(b.CSRC, "bgemm_api.cpp"), os.path.join(b.CSRC, "bgemm_kernels.hip")],
-                 path, extra=defs)
+        b._hipcc(b.SOURCES, path, extra=defs)
         return path
 
     with ThreadPoolExecutor(max(1, min(8, os.cpu_count() or 1))) as ex:

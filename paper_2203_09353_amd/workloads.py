@@ -13,6 +13,9 @@ kernels cannot rely on contiguity):
   s512 : 5,000 x 512^3, alpha = beta = 1, A_i = Qa diag(da) Qa^T and
          B_i = Qb diag(db) Qb^T (Q from a pool of Haar orthogonal matrices,
          d uniform[-1, 1)), C uniform, seed 3
+  w256 : 20,000 x 256^3, alpha 1, beta 0, entries s m 2^e (m uniform in
+         [1, 2), e uniform in -20..20, s = +-1), C = NaN, seed 5 -- the
+         input of the precision modes
   vb   : 100,000 variable sizes, m, n, k independently 2^j + delta with j
          uniform in 3..9 and delta uniform in {-1, 0, 1}; alpha 1, beta 0.5;
          ld = rows (``vb``) or rows rounded up to a multiple of 8 (``vb8``);
@@ -115,12 +118,21 @@ def _fill_uniform(t: torch.Tensor, seed: int, stream: int, chunk: int = 1 << 26)
         flat[off:off + n] = inputs.uniform_flat(seed, stream, off, n, device=t.device)
 
 
-def uniform_part(name, batch, m, n, k, alpha, beta, seed, device="cuda", c_nan=False):
+def _fill_wide(t: torch.Tensor, seed: int, stream: int, chunk: int = 1 << 25):
+    flat = t.view(-1)
+    for off in range(0, flat.numel(), chunk):
+        n = min(chunk, flat.numel() - off)
+        flat[off:off + n] = inputs.wide_flat(seed, stream, off, n, device=t.device)
+
+
+def uniform_part(name, batch, m, n, k, alpha, beta, seed, device="cuda", c_nan=False,
+                 wide=False):
     A = torch.empty(batch, k, m, dtype=torch.float64, device=device)
     B = torch.empty(batch, n, k, dtype=torch.float64, device=device)
     C = torch.empty(batch, n, m, dtype=torch.float64, device=device)
-    _fill_uniform(A, seed, 0)
-    _fill_uniform(B, seed, 1)
+    fill = _fill_wide if wide else _fill_uniform
+    fill(A, seed, 0)
+    fill(B, seed, 1)
     if c_nan:
         C.fill_(float("nan"))
     else:
@@ -235,11 +247,13 @@ PARTS = {
     "u64": lambda d, b: uniform_part("u64", b(200_000), 64, 64, 64, 1.0, 1.0, 1, d),
     "u256": lambda d, b: uniform_part("u256", b(20_000), 256, 256, 256, 1.0, 1.0, 2, d),
     "s512": lambda d, b: symmetric_part("s512", b(5_000), 512, 1.0, 1.0, 3, d),
+    "w256": lambda d, b: uniform_part("w256", b(20_000), 256, 256, 256, 1.0, 0.0, 5, d,
+                                      c_nan=True, wide=True),
     "vb": lambda d, b: vb_part("vb", b(100_000), 1.0, 0.5, 4, False, d),
     "vb8": lambda d, b: vb_part("vb8", b(100_000), 1.0, 0.5, 4, True, d),
 }
 ALIASES = {"config1": "u32", "config2": "u64+u256+s512", "config3": "vb",
-           "config2+vb": "u64+u256+s512+vb"}
+           "config2+vb": "u64+u256+s512+vb", "config4": "w256"}
 
 
 def build(name: str, device="cuda", scale: float = 1.0):

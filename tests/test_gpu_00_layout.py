@@ -48,3 +48,40 @@ def test_mfma_4x4x4_lane_layout():
             for j in range(4):
                 want[16 * i + 4 * blk + j] = D[blk, i, j]
     assert np.array_equal(d, want)
+
+
+def test_mfma_f32_16x16x4_lane_layout():
+    """v_mfma_f32_16x16x4_f32 (precision mode fp32): lane l holds A(l%16, l/16)
+    and B(l/16, l%16); result register v of lane l is D(4 (l/16) + v, l%16)."""
+    from paper_2203_09353_amd import microbench
+    rng = np.random.default_rng(2)
+    Am = rng.integers(-8, 9, (16, 4)).astype(np.float32)
+    Bm = rng.integers(-8, 9, (4, 16)).astype(np.float32)
+    Cm = rng.integers(-8, 9, (16, 16)).astype(np.float32)
+    lanes = np.arange(64)
+    a = Am[lanes % 16, lanes // 16]
+    b = Bm[lanes // 16, lanes % 16]
+    c = np.stack([Cm[4 * (lanes // 16) + v, lanes % 16] for v in range(4)], axis=1)
+    d = microbench.mfma_f32_once(a, b, c).numpy()
+    D = Am @ Bm + Cm
+    want = np.stack([D[4 * (lanes // 16) + v, lanes % 16] for v in range(4)], axis=1)
+    assert np.array_equal(d, want)
+
+
+def test_mfma_bf16_16x16x32_lane_layout():
+    """v_mfma_f32_16x16x32_bf16 (precision modes bf16 and emulated): lane l
+    holds A(l%16, 8 (l/16) + e) and B(8 (l/16) + e, l%16), e = 0..7; result
+    register v of lane l is D(4 (l/16) + v, l%16)."""
+    from paper_2203_09353_amd import microbench
+    rng = np.random.default_rng(3)
+    Am = rng.integers(-8, 9, (16, 32)).astype(np.float32)
+    Bm = rng.integers(-8, 9, (32, 16)).astype(np.float32)
+    Cm = rng.integers(-8, 9, (16, 16)).astype(np.float32)
+    lanes = np.arange(64)
+    a = np.stack([Am[lanes % 16, 8 * (lanes // 16) + e] for e in range(8)], axis=1)
+    b = np.stack([Bm[8 * (lanes // 16) + e, lanes % 16] for e in range(8)], axis=1)
+    c = np.stack([Cm[4 * (lanes // 16) + v, lanes % 16] for v in range(4)], axis=1)
+    d = microbench.mfma_bf16_once(a, b, c).numpy()
+    D = Am @ Bm + Cm
+    want = np.stack([D[4 * (lanes // 16) + v, lanes % 16] for v in range(4)], axis=1)
+    assert np.array_equal(d, want)

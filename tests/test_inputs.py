@@ -68,3 +68,17 @@ def test_haar_orthogonal():
     eye = torch.eye(16, dtype=torch.float64)
     for i in range(3):
         assert torch.allclose(q[i] @ q[i].T, eye, atol=1e-13)
+
+
+def test_wide_values_support_and_exponents():
+    x = inputs.wide_flat(9, 2, 0, 200_000, emax=20)
+    m, e = torch.frexp(x)
+    assert torch.all((e - 1 >= -20) & (e - 1 <= 20))
+    assert set((e - 1).unique().tolist()) == set(range(-20, 21))
+    assert torch.all((m.abs() >= 0.5) & (m.abs() < 1.0))
+    frac_neg = (x < 0).double().mean().item()
+    assert abs(frac_neg - 0.5) < 0.01
+    # significand 2|m| - 1 uniform on [0, 1)
+    sig = 2 * m.abs() - 1
+    assert abs(sig.mean().item() - 0.5) < 0.01
+    assert torch.equal(inputs.wide_flat(9, 2, 1000, 10), x[1000:1010])

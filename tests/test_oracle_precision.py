@@ -107,3 +107,34 @@ def test_reference_products_of_rounded_inputs():
     ta = torch.tensor(A).float().bfloat16().double().numpy()
     tb = torch.tensor(B).float().bfloat16().double().numpy()
     assert np.array_equal(rb, ta @ tb)
+
+
+def test_dot2_against_exact_rationals():
+    # Ogita-Rump-Oishi bound: |res - exact| <= u |exact| + gamma_k^2 (|A||B|)
+    u = 2.0 ** -53
+    for trial in range(4):
+        m, k, n = 3, 37, 4
+        A = rng.uniform(-1, 1, (m, k)) * 2.0 ** rng.integers(-30, 31, (m, k))
+        B = rng.uniform(-1, 1, (k, n)) * 2.0 ** rng.integers(-30, 31, (k, n))
+        R = P.dot2_gemm(A, B)
+        g = k * u / (1 - k * u)
+        mag = np.abs(A) @ np.abs(B)
+        for i in range(m):
+            for j in range(n):
+                exact = sum(Fraction(float(A[i, p])) * Fraction(float(B[p, j])) for p in range(k))
+                err = abs(Fraction(float(R[i, j])) - exact)
+                assert err <= Fraction(u) * abs(exact) + Fraction(g * g * float(mag[i, j]))
+
+
+def test_dot2_cancellation_beyond_binary64():
+    # exact result 1; a plain binary64 sum in this order returns 0
+    A = np.array([[1e16, 1.0, -1e16]])
+    B = np.ones((3, 1))
+    assert (1e16 + 1.0) - 1e16 == 0.0
+    assert P.dot2_gemm(A, B)[0, 0] == 1.0
+    # error-free transformations are exact
+    a, b = 0.1, 3.0 ** -20
+    s, e = P._two_sum(a, b)
+    assert Fraction(s) + Fraction(e) == Fraction(a) + Fraction(b)
+    p, e = P._two_product(a, b)
+    assert Fraction(p) + Fraction(e) == Fraction(a) * Fraction(b)
