@@ -45,13 +45,14 @@ class BgemmError(RuntimeError):
 
 
 def lib(path: str | None = None):
-    """Loads libbgemm.so (raises if it has not been built).  ``path`` selects
-    another build of the same interface (e.g. a tuning variant); it must be
-    given before the first call."""
+    """Loads libbgemm.so (raises if it has not been built).  ``path``, or else
+    the environment variable BG_LIB, selects another build of the same
+    interface (e.g. a tuning variant); it must be given before the first
+    call."""
     global _lib
     if _lib is not None:
         return _lib
-    path = path or LIB_PATH
+    path = path or os.environ.get("BG_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError("libbgemm.so not built: run python -m paper_2203_09353_amd.build")
     L = ctypes.CDLL(path)

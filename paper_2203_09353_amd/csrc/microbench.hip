@@ -151,7 +151,76 @@ static float time_ms(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
+// LDS access cost probe: one wave issues `iters` x 8 LDS instructions of one
+// kind, every lane at its own byte offset (< 8 KB, aligned to the access
+// width) plus 8 KB x u for the u-th instruction of a group (the bank pattern
+// repeats every 256 bytes, so all eight see the same banks).  Writes the
+// elapsed shader clock cycles to *cycles.
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+template <int KIND>
+__global__ __launch_bounds__(64) void k_lds_probe(const int* offs, int iters, long long* cycles,
+                                                  int* sink) {
+  __shared__ __align__(16) int lds[16384];   // 64 KB
+  for (int i = threadIdx.x; i < 16384; i += 64) lds[i] = i;
+  __syncthreads();
+  const unsigned addr = (unsigned)(size_t)(__attribute__((address_space(3))) int*)lds + offs[threadIdx.x];
+  v4i acc4 = {0, 0, 0, 0};
+  v2i acc2 = {0, 0};
+  const v4i w4 = {1, 2, 3, 4};
+  const v2i w2 = {1, 2};
+  __builtin_amdgcn_s_waitcnt(0);
+  const long long t0 = __builtin_readcyclecounter();
+  for (int it = 0; it < iters; ++it) {
+    // the wait names the read results as operands, so nothing uses them
+    // before the loads have landed
+    if constexpr (KIND == 0) {
+      v2i r0, r1, r2, r3, r4, r5, r6, r7;
+#define RD(R, U) asm volatile("ds_read_b64 %0, %1 offset:%2" : "=v"(R) : "v"(addr), "i"(U * 8192));
+      RD(r0, 0) RD(r1, 1) RD(r2, 2) RD(r3, 3) RD(r4, 4) RD(r5, 5) RD(r6, 6) RD(r7, 7)
+#undef RD
+      asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(r0), "+v"(r1), "+v"(r2), "+v"(r3), "+v"(r4),
+                   "+v"(r5), "+v"(r6), "+v"(r7) : : "memory");
+      acc2 ^= r0 ^ r1 ^ r2 ^ r3 ^ r4 ^ r5 ^ r6 ^ r7;
+    } else if constexpr (KIND == 1) {
+      v4i r0, r1, r2, r3, r4, r5, r6, r7;
+#define RD(R, U) asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(R) : "v"(addr), "i"(U * 8192));
+      RD(r0, 0) RD(r1, 1) RD(r2, 2) RD(r3, 3) RD(r4, 4) RD(r5, 5) RD(r6, 6) RD(r7, 7)
+#undef RD
+      asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(r0), "+v"(r1), "+v"(r2), "+v"(r3), "+v"(r4),
+                   "+v"(r5), "+v"(r6), "+v"(r7) : : "memory");
+      acc4 ^= r0 ^ r1 ^ r2 ^ r3 ^ r4 ^ r5 ^ r6 ^ r7;
+    } else {
+#define WR(U)                                                                              \
+      if constexpr (KIND == 2)                                                             \
+        asm volatile("ds_write_b64 %0, %1 offset:%2" : : "v"(addr), "v"(w2), "i"(U * 8192)); \
+      else                                                                                 \
+        asm volatile("ds_write_b128 %0, %1 offset:%2" : : "v"(addr), "v"(w4), "i"(U * 8192));
+      WR(0) WR(1) WR(2) WR(3) WR(4) WR(5) WR(6) WR(7)
+#undef WR
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    }
+  }
+  const long long t1 = __builtin_readcyclecounter();
+  if (threadIdx.x == 0) *cycles = t1 - t0;
+  sink[threadIdx.x] = acc4.x + acc4.y + acc4.z + acc4.w + acc2.x + acc2.y;
+}
+
 extern "C" {
+
+// kind: 0 ds_read_b64, 1 ds_read_b128, 2 ds_write_b64, 3 ds_write_b128.
+// offs: 64 device ints, each in [0, 8192 - width] and a multiple of the
+// width (checked by the caller).  Returns 0 on success.
+int mb_lds_probe(int kind, const int* offs, int iters, long long* cycles, int* sink) {
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(k_lds_probe<0>, dim3(1), dim3(64), 0, 0, offs, iters, cycles, sink); break;
+    case 1: hipLaunchKernelGGL(k_lds_probe<1>, dim3(1), dim3(64), 0, 0, offs, iters, cycles, sink); break;
+    case 2: hipLaunchKernelGGL(k_lds_probe<2>, dim3(1), dim3(64), 0, 0, offs, iters, cycles, sink); break;
+    default: hipLaunchKernelGGL(k_lds_probe<3>, dim3(1), dim3(64), 0, 0, offs, iters, cycles, sink); break;
+  }
+  return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
+}
 
 int mb_mfma_f64_16x16x4(const double* a, const double* b, const double* c, double* d) {
   hipLaunchKernelGGL(k_mfma_once, dim3(1), dim3(64), 0, 0, a, b, c, d);

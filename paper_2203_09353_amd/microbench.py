@@ -31,6 +31,8 @@ def lib():
         L.mb_mfma_bf16_16x16x32.argtypes = [vp, vp, vp, vp]
         L.mb_mfma_f64_4x4x4.restype = ctypes.c_int
         L.mb_mfma_f64_4x4x4.argtypes = [vp, vp, vp, vp, ctypes.c_int]
+        L.mb_lds_probe.restype = ctypes.c_int
+        L.mb_lds_probe.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, vp]
         L.mb_fp64_peak_ms.restype = ctypes.c_double
         L.mb_fp64_peak_ms.argtypes = [ctypes.c_int] * 4 + [vp]
         L.mb_stream_ms.restype = ctypes.c_double
@@ -125,6 +127,26 @@ def stream_gbps(kind: str, nbytes: int = 4 << 30, grid: int | None = None, reps:
     moved = nbytes * (2 if kind == "copy" else 1) * reps
     del src, dst
     return moved / (ms * 1e-3) / 1e9, ms
+
+
+LDS_KINDS = {"read_b64": (0, 8), "read_b128": (1, 16), "write_b64": (2, 8), "write_b128": (3, 16)}
+
+
+def lds_cycles(offsets, kind: str, iters: int = 2000) -> float:
+    """Shader clock cycles per LDS instruction of `kind` when lane l accesses
+    byte offset offsets[l] (one wave, eight independent instructions in
+    flight between waits)."""
+    code, width = LDS_KINDS[kind]
+    offs = [int(o) for o in offsets]
+    if len(offs) != 64 or any(o < 0 or o > 8192 - width or o % width for o in offs):
+        raise ValueError("64 offsets in [0, 8192 - width], multiples of the width")
+    d = torch.tensor(offs, dtype=torch.int32, device="cuda")
+    cyc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sink = torch.zeros(64, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        if lib().mb_lds_probe(code, d.data_ptr(), iters, cyc.data_ptr(), sink.data_ptr()) != 0:
+            raise RuntimeError("mb_lds_probe failed")
+    return float(cyc.item()) / (8 * iters)
 
 
 def summary():

@@ -173,7 +173,7 @@ def symmetric_part(name, batch, size, alpha, beta, seed, device="cuda", pool=DEF
     return part
 
 
-def vb_part(name, batch, alpha, beta, seed, pad8=False, device="cuda"):
+def vb_part(name, batch, alpha, beta, seed, pad8=False, device="cuda", group=4096):
     ms = inputs.log_uniform_sizes(seed, 0, batch)
     ns = inputs.log_uniform_sizes(seed, 1, batch)
     ks = inputs.log_uniform_sizes(seed, 2, batch)
@@ -192,7 +192,7 @@ def vb_part(name, batch, alpha, beta, seed, pad8=False, device="cuda"):
             slab.fill_(float("nan"))
             # payload counters run over rows * cols per instance, as in
             # inputs.uniform_ragged; padding keeps NaN
-            _fill_padded(slab, o, rows, cols, ld, seed, stream, device)
+            _fill_padded(slab, o, rows, cols, ld, seed, stream, device, group)
         else:
             _fill_uniform(slab, seed, stream)
         slabs.append(slab)
@@ -218,7 +218,7 @@ def _fill_padded(slab, o, rows, cols, ld, seed, stream, device, group=4096):
         e = min(batch, s + group)
         vals = inputs.uniform_flat(seed, stream, int(poff[s]), int(poff[e] - poff[s]), device)
         # destination index of each payload element
-        r_all, c_all, l_all, b_all = (x[s:e].to(device) for x in (rows, cols, ld, o[s:e]))
+        r_all, c_all, l_all, b_all = (x[s:e].to(device) for x in (rows, cols, ld, o[:-1]))
         cnt = (r_all * c_all)
         inst = torch.repeat_interleave(torch.arange(e - s, device=device), cnt)
         local = torch.arange(vals.numel(), device=device) - torch.repeat_interleave(

@@ -4,6 +4,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 import bench
 from paper_2203_09353_amd import profile_summary
 
@@ -44,3 +46,19 @@ def test_part_attribution_of_dispatches():
     assert profile_summary.part_of("void bg::k_uniform<bg::Cfg<64, 64, 16>>", 0) == "u64"
     assert profile_summary.part_of("void bg::k_uniform<bg::Cfg<128, 64, 16>>", 0) == "u256"
     assert profile_summary.part_of("void bg::k_uniform<bg::Cfg<128, 64, 16>>", 1) == "s512"
+
+
+def test_padded_variable_size_workload_across_fill_groups():
+    """ld rounded up to 8: every instance's payload (also past the first fill
+    group) is the generator's, padding rows are NaN."""
+    from paper_2203_09353_amd import inputs, workloads
+    p = workloads.vb_part("vb8", 300, 1.0, 0.5, 4, pad8=True, device="cpu", group=128)
+    ms, ns, ks, la, lb, lc = p.sizes_host
+    pay = ms * ks
+    for i in (0, 127, 128, 200, p.batch - 1):
+        A, _, _ = workloads.host_instance(p, i)
+        m, k = int(ms[i]), int(ks[i])
+        assert int(la[i]) % 8 == 0 and int(la[i]) >= m
+        ref = inputs.uniform_flat(4, 0, int(pay[:i].sum()), m * k).view(k, m).numpy()
+        assert np.array_equal(A[:, :m], ref)
+        assert np.isnan(A[:, m:]).all()

@@ -174,3 +174,60 @@ def test_pipelined_path_odd_extents_even_ld(h, m, n, k, ta, tb):
     # tight even ld where the extent is even
     if a_rows % 2 == 0 and b_rows % 2 == 0 and m % 2 == 0:
         run_case(h, ta, tb, m, n, k, 1.0, 0.0, pads=(0, 0, 0), cls=2, batch=2)
+
+
+@pytest.mark.parametrize("m,n,k", [(65, 63, 17), (129, 131, 33), (7, 9, 13), (130, 66, 64)])
+@pytest.mark.parametrize("ta,tb", list(itertools.product("NT", "NT")))
+def test_odd_ld_and_unaligned_operands_in_the_pipelined_class(h, m, n, k, ta, tb):
+    """Odd leading dimensions and operands that start 8 bytes past a 16-byte
+    boundary, in the 128-tile class (whose pipelined path needs 16-byte
+    aligned pairs; such tiles must take its other path)."""
+    run_case(h, ta, tb, m, n, k, 1.0, 0.5, pads=(1, 3, 1), cls=2, batch=3)
+    run_case(h, ta, tb, m, n, k, -2.0, 1.0, pads=(2, 1, 0), cls=2, batch=3, integer=True, seed=9)
+    # instance 0 of a stacked batch shifted by one double: every operand
+    # pointer is only 8-byte aligned
+    A, B, C, ash, bsh = _make(13, ta, tb, m, n, k, 2, (2, 2, 2), False)
+    sh = lambda X: torch.cat([torch.zeros(1, dtype=torch.float64), X.reshape(-1)]).cuda()
+    fa, fb, fc = sh(A), sh(B), sh(C)
+    per = lambda X: X.shape[1] * X.shape[2]
+    pA = torch.tensor([fa.data_ptr() + 8 + 8 * i * per(A) for i in range(2)], device="cuda")
+    pB = torch.tensor([fb.data_ptr() + 8 + 8 * i * per(B) for i in range(2)], device="cuda")
+    pC = torch.tensor([fc.data_ptr() + 8 + 8 * i * per(C) for i in range(2)], device="cuda")
+    h.set_uniform_class(2)
+    try:
+        st = h.dgemm_batched_raw(ta, tb, m, n, k, 0.75, pA.data_ptr(), A.shape[2], pB.data_ptr(),
+                                 B.shape[2], -0.5, pC.data_ptr(), C.shape[2], 2)
+        torch.cuda.synchronize()
+    finally:
+        h.set_uniform_class(-1)
+    assert st == 0
+    got = fc[1:].cpu().numpy().reshape(C.shape)
+    ref = oracle_uniform(ta, tb, m, n, k, 0.75, A.numpy(), B.numpy(), -0.5, C.numpy())
+    for i in range(2):
+        check_instance(got[i, :, :m].T, ref[i, :, :m].T, op_view(A.numpy()[i], *ash, ta),
+                       op_view(B.numpy()[i], *bsh, tb), C.numpy()[i, :, :m].T, 0.75, -0.5,
+                       where="shifted inst %d" % i)
+
+
+def test_huge_leading_dimension(h):
+    """A leading dimension so large that one 128-row tile spans more than
+    2 GB: 64-bit addressing throughout, results as the oracle's."""
+    m, n, k, lda = 130, 40, 20, 2_200_000          # A stored k x m ('T'), 2.3 GB
+    A = torch.full((1, m, lda), float("nan"), dtype=torch.float64, device="cuda")
+    Ac = inputs.uniform_batch(71, 0, 1, k, m, k)    # compact copy for the oracle
+    A[:, :, :k] = Ac.cuda()
+    B = inputs.uniform_batch(71, 1, 1, k, n, k)
+    C = inputs.uniform_batch(71, 2, 1, m, n, m)
+    Cd = C.cuda()
+    h.set_uniform_class(2)
+    try:
+        h.batched(A, B.cuda(), Cd, m, n, k, 1.0, 0.5, "T", "N")
+        torch.cuda.synchronize()
+    finally:
+        h.set_uniform_class(-1)
+    del A
+    got = Cd.cpu().numpy()
+    ref = oracle_uniform("T", "N", m, n, k, 1.0, Ac.numpy(), B.numpy(), 0.5, C.numpy())
+    check_instance(got[0, :, :m].T, ref[0, :, :m].T, op_view(Ac.numpy()[0], k, m, "T"),
+                   op_view(B.numpy()[0], k, n, "N"), C.numpy()[0, :, :m].T, 1.0, 0.5,
+                   where="huge lda")
