@@ -2,6 +2,7 @@
 
     python bench.py [--steps K] [--warmup W] [--workload config2+vb]
     python bench.py --workload config4 [--modes fp64,fp32,bf16,emu3,emu6,emu7]
+    python bench.py --workload config5 [--rates 1000,5000,20000,50000] [--duration 2]
 
 A step is one pass over every part of the workload: the three uniform
 batches of 64^3, 256^3 and 512^3 (symmetric) instances through
@@ -14,6 +15,12 @@ are seeded synthetic matrices already resident in HBM.  Prints one JSON line.
 binary64-equivalent GFLOP/s and the error on sampled instances against the
 binary64 oracle and a compensated (Dot2) reference; ``value`` is the fastest
 mode that reaches binary64 accuracy (relative Frobenius error <= 1e-13).
+
+``--workload config5`` drives the request loop (include/bgserve.h): 64
+clients with states of 2^k x 2^k (k uniform in 5..9), Poisson arrivals at each
+offered rate for ``--duration`` seconds, chains of 1..16 products whose
+factors are generated on the device; per rate the achieved GFLOP/s and the
+p50 / p99 request latency; ``value`` is the GFLOP/s at the highest rate.
 """
 from __future__ import annotations
 
@@ -227,6 +234,81 @@ def precision_cpu_baseline(p, mode, seconds):
                 n, p.batch, p.name, t)}
 
 
+def serving_bench(args, h):
+    """The config5 line: the request loop at each offered rate."""
+    import numpy as np
+    import torch
+    from oracle import serving
+    from paper_2203_09353_amd import serve
+
+    clients, seed = 64, 5
+    sizes = serve.client_sizes(seed, clients)
+    srv = serve.Server(h, sizes, seed=seed, budget=64 << 30)
+    rows = []
+    try:
+        # warm-up: one short schedule
+        a, c, l = serve.requests(seed + 100, clients, 2000.0, 0.05)
+        srv.run(a, c, l)
+        for rate in [float(x) for x in args.rates.split(",")]:
+            srv.reset()
+            a, c, l = serve.requests(seed, clients, rate, args.duration)
+            st, fi, ticks = srv.run(a, c, l)
+            n = sizes[c].astype(np.float64)
+            flops = float((2.0 * n ** 3 * l).sum())
+            wall = float(fi.max())
+            lat = (fi - a) * 1e3
+            row = {"offered_req_s": rate, "requests": int(len(a)),
+                   "achieved_req_s": round(len(a) / wall, 1), "gflops": round(flops / wall / 1e9, 1),
+                   "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                   "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                   "ticks": int(ticks), "mean_batch": round(float(l.sum()) / max(ticks, 1), 2),
+                   "wall_s": round(wall, 3)}
+            log(json.dumps(row))
+            rows.append(row)
+        # parity: one client of the last run against the CPU replay
+        prods = serving.products_per_client(clients, c, l)
+        cl = int(np.argmin(np.where(prods > 0, sizes * 1000 + prods, 1 << 40)))
+        S, p = srv.state(cl)
+        ref = serving.final_state(seed, cl, int(sizes[cl]), int(p))
+        parity = float(np.linalg.norm(S - ref) / np.linalg.norm(ref))
+    finally:
+        srv.close()
+    top = rows[-1]
+    roof = {"bound": "mfma", "achieved": round(top["gflops"] / 1e3, 3), "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = None
+    roof["kernel"] = "request loop at %g req/s (factor generation + batched GEMMs)" % top[
+        "offered_req_s"]
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU replay on a sample")
+        t0 = time.perf_counter()
+        done, fl = 0, 0.0
+        order = np.argsort(sizes[c], kind="stable")
+        for r in order:
+            nn = int(sizes[c[r]])
+            serving.final_state(seed, int(c[r]), nn, int(l[r]))
+            done += 1
+            fl += 2.0 * nn ** 3 * l[r]
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+        t = time.perf_counter() - t0
+        cpu = {"value": round(fl / t / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": "%d requests of the last rate, smallest states first, factors from the "
+                         "Philox oracle, %.1f s" % (done, t)}
+    out = {"metric": METRIC, "value": top["gflops"], "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": len(rows), "warmup": 1, "ms_per_step": round(top["wall_s"] * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (Poisson arrivals, factors from a Philox4x64-10 stream on the device)",
+           "config": {"workload": "config5", "clients": clients,
+                      "state_sizes": sorted(set(int(x) for x in sizes)),
+                      "duration_s": args.duration},
+           "roofline": roof, "cpu_baseline": cpu, "rates": rows,
+           "parity_rel_fro_one_client": parity}
+    print(json.dumps(out), flush=True)
+
+
 def sampled_parity(h, parts, per_part, seed=11):
     """Runs one step and compares `per_part` seeded instances of every part
     with the CPU oracle (inputs copied to the host before the call)."""
@@ -328,6 +410,10 @@ def main():
     ap.add_argument("--check", type=int, default=3, help="sampled parity instances per part")
     ap.add_argument("--modes", default="fp64,fp32,bf16,emu3,emu6,emu7",
                     help="precision modes timed by --workload config4")
+    ap.add_argument("--rates", default="1000,5000,20000,50000",
+                    help="offered request rates (per second) for --workload config5")
+    ap.add_argument("--duration", type=float, default=2.0,
+                    help="seconds of arrivals per rate for --workload config5")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -345,6 +431,9 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     h = bgemm.Handle()
+    if args.workload == "config5":
+        serving_bench(args, h)
+        return
     log("building workload %s" % args.workload)
     t0 = time.perf_counter()
     parts = workloads.build(args.workload, "cuda")

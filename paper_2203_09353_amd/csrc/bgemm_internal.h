@@ -72,4 +72,24 @@ size_t vbatched_workspace_bytes(int batch);
 hipError_t launch_vbatched(const VbatchedArgs& a, const VbWorkspace& ws, int num_cus,
                            hipStream_t s);
 
+// Request loop: one generated factor (column-major n x n at `out`; factor j of
+// `client`, values scaled by `scale`).
+struct FillJob {
+  double* out;
+  long long j;
+  int n;
+  int client;
+  double scale;
+};
+
+// Generates the factors of njobs jobs (device array) in one launch; max_n is
+// the largest n among them.
+hipError_t launch_fill_factors(const FillJob* d_jobs, int njobs, int max_n,
+                               unsigned long long seed, hipStream_t s);
+// One factor, the same generator (host-side job).
+hipError_t launch_fill_one(double* out, int n, int client, long long j, double scale,
+                           unsigned long long seed, hipStream_t s);
+// out <- identity (n x n, column-major, ld = n).
+hipError_t launch_identity(double* out, int n, hipStream_t s);
+
 }  // namespace bg

@@ -1,0 +1,321 @@
+// Request loop over the batched GEMM (continuous batching of per-client
+// product chains).  Host code: the scheduler, the tick loop and the C ABI of
+// include/bgserve.h; the generator and identity kernels live in
+// serve_kernels.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <deque>
+#include <limits>
+#include <thread>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/bgserve.h"
+#include "bgemm_internal.h"
+
+namespace bs {
+
+// Per-client FIFO queues and the one active request of each client.  Pure
+// host logic, shared by the device loop and the virtual-clock replay.
+struct Scheduler {
+  int nc = 0, nreq = 0;
+  const double* arrival = nullptr;
+  const int* client = nullptr;
+  const int* length = nullptr;
+  double* start = nullptr;
+  double* finish = nullptr;
+  std::vector<std::deque<int>> queue;
+  std::vector<int> active, remaining;
+  std::vector<int> batch;   // clients served by the current tick, ascending
+  int next = 0, finished = 0;
+
+  void init(int num_clients, int n, const double* arr, const int* cl, const int* len, double* st,
+            double* fin) {
+    nc = num_clients; nreq = n; arrival = arr; client = cl; length = len; start = st; finish = fin;
+    queue.assign(nc, {});
+    active.assign(nc, -1);
+    remaining.assign(nc, 0);
+    batch.clear();
+    next = finished = 0;
+  }
+  void admit(double now) {
+    while (next < nreq && arrival[next] <= now) queue[client[next]].push_back(next++);
+  }
+  // Starts the oldest queued request of every idle client; the tick serves
+  // every client with an active request.
+  int begin_tick(double now) {
+    batch.clear();
+    for (int c = 0; c < nc; ++c) {
+      if (active[c] < 0 && !queue[c].empty()) {
+        const int r = queue[c].front();
+        queue[c].pop_front();
+        active[c] = r;
+        remaining[c] = length[r];
+        start[r] = now;
+      }
+      if (active[c] >= 0) batch.push_back(c);
+    }
+    return (int)batch.size();
+  }
+  void end_tick(double now) {
+    for (int c : batch)
+      if (--remaining[c] == 0) {
+        finish[active[c]] = now;
+        active[c] = -1;
+        ++finished;
+      }
+  }
+  bool done() const { return finished == nreq; }
+  double next_arrival() const {
+    return next < nreq ? arrival[next] : std::numeric_limits<double>::infinity();
+  }
+};
+
+static bool valid_schedule(int nc, int n, const double* arr, const int* cl, const int* len) {
+  if (n < 0 || (n > 0 && (!arr || !cl || !len))) return false;
+  for (int r = 0; r < n; ++r) {
+    if (!(arr[r] >= 0.0) || (r > 0 && arr[r] < arr[r - 1])) return false;
+    if (cl[r] < 0 || cl[r] >= nc || len[r] < 1) return false;
+  }
+  return true;
+}
+
+}  // namespace bs
+
+struct bs_server {
+  unsigned magic;
+  bg_handle_t h;
+  int device;
+  int nc;
+  unsigned long long seed;
+  std::vector<int> sizes;
+  std::vector<double> scale;
+  std::vector<double*> st[2];
+  std::vector<double*> fac;
+  std::vector<int> cur;
+  std::vector<long long> products;
+  bg::FillJob* d_jobs;
+  bg::FillJob* h_jobs;            // pinned
+  const double** d_ptrs;
+  const double** h_ptrs;          // pinned
+};
+
+static const unsigned kServerMagic = 0x5E7BE5E7u;
+static bool valid(bs_server_t s) { return s && s->magic == kServerMagic; }
+
+static size_t client_bytes(int n) { return 3 * (size_t)n * (size_t)n * sizeof(double); }
+
+static void free_all(bs_server* s) {
+  for (int b = 0; b < 2; ++b)
+    for (double* p : s->st[b]) if (p) (void)hipFree(p);
+  for (double* p : s->fac) if (p) (void)hipFree(p);
+  if (s->d_jobs) (void)hipFree(s->d_jobs);
+  if (s->d_ptrs) (void)hipFree((void*)s->d_ptrs);
+  if (s->h_jobs) (void)hipHostFree(s->h_jobs);
+  if (s->h_ptrs) (void)hipHostFree((void*)s->h_ptrs);
+}
+
+static hipError_t set_identity(bs_server* s, hipStream_t stream) {
+  for (int c = 0; c < s->nc; ++c) {
+    const hipError_t e = bg::launch_identity(s->st[s->cur[c]][c], s->sizes[c], stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipStreamSynchronize(stream);
+}
+
+extern "C" {
+
+unsigned long long bs_bytes_needed(int num_clients, const int* sizes) {
+  if (num_clients <= 0 || !sizes) return 0;
+  unsigned long long t = 0;
+  for (int c = 0; c < num_clients; ++c)
+    if (sizes[c] > 0) t += client_bytes(sizes[c]);
+  t += (unsigned long long)num_clients * (sizeof(bg::FillJob) + 3 * sizeof(double*));
+  return t;
+}
+
+bg_status_t bs_create(bg_handle_t h, int num_clients, const int* sizes, unsigned long long seed,
+                      unsigned long long budget, bs_server_t* out) {
+  if (!out || !h || num_clients <= 0 || num_clients > 65535 || !sizes) return BG_STATUS_INVALID_VALUE;
+  for (int c = 0; c < num_clients; ++c)
+    if (sizes[c] < 1 || sizes[c] > 4096) return BG_STATUS_INVALID_VALUE;
+  if (budget && bs_bytes_needed(num_clients, sizes) > budget) return BG_STATUS_ALLOC_FAILED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return BG_STATUS_DEVICE_ERROR;
+  bs_server* s = new bs_server();
+  s->magic = kServerMagic;
+  s->h = h;
+  s->device = dev;
+  s->nc = num_clients;
+  s->seed = seed;
+  s->sizes.assign(sizes, sizes + num_clients);
+  s->scale.resize(num_clients);
+  s->st[0].assign(num_clients, nullptr);
+  s->st[1].assign(num_clients, nullptr);
+  s->fac.assign(num_clients, nullptr);
+  s->cur.assign(num_clients, 0);
+  s->products.assign(num_clients, 0);
+  bool ok = true;
+  for (int c = 0; c < num_clients && ok; ++c) {
+    const size_t b = (size_t)sizes[c] * sizes[c] * sizeof(double);
+    s->scale[c] = std::sqrt(3.0 / (double)sizes[c]);
+    ok = hipMalloc(&s->st[0][c], b) == hipSuccess && hipMalloc(&s->st[1][c], b) == hipSuccess &&
+         hipMalloc(&s->fac[c], b) == hipSuccess;
+  }
+  ok = ok && hipMalloc(&s->d_jobs, num_clients * sizeof(bg::FillJob)) == hipSuccess &&
+       hipMalloc((void**)&s->d_ptrs, 3 * num_clients * sizeof(double*)) == hipSuccess &&
+       hipHostMalloc((void**)&s->h_jobs, num_clients * sizeof(bg::FillJob)) == hipSuccess &&
+       hipHostMalloc((void**)&s->h_ptrs, 3 * num_clients * sizeof(double*)) == hipSuccess;
+  if (!ok) {
+    free_all(s);
+    s->magic = 0;
+    delete s;
+    return BG_STATUS_ALLOC_FAILED;
+  }
+  void* stream = nullptr;
+  bg_get_stream(h, &stream);
+  if (set_identity(s, (hipStream_t)stream) != hipSuccess) {
+    free_all(s);
+    s->magic = 0;
+    delete s;
+    return BG_STATUS_DEVICE_ERROR;
+  }
+  *out = s;
+  return BG_STATUS_SUCCESS;
+}
+
+bg_status_t bs_destroy(bs_server_t s) {
+  if (!valid(s)) return BG_STATUS_INVALID_HANDLE;
+  (void)hipDeviceSynchronize();
+  free_all(s);
+  s->magic = 0;
+  delete s;
+  return BG_STATUS_SUCCESS;
+}
+
+bg_status_t bs_reset(bs_server_t s) {
+  if (!valid(s)) return BG_STATUS_INVALID_HANDLE;
+  void* stream = nullptr;
+  bg_get_stream(s->h, &stream);
+  for (int c = 0; c < s->nc; ++c) {
+    s->cur[c] = 0;
+    s->products[c] = 0;
+  }
+  return set_identity(s, (hipStream_t)stream) == hipSuccess ? BG_STATUS_SUCCESS
+                                                             : BG_STATUS_DEVICE_ERROR;
+}
+
+bg_status_t bs_state(bs_server_t s, int c, double* host_out, long long* products) {
+  if (!valid(s)) return BG_STATUS_INVALID_HANDLE;
+  if (c < 0 || c >= s->nc || !host_out) return BG_STATUS_INVALID_VALUE;
+  const size_t b = (size_t)s->sizes[c] * s->sizes[c] * sizeof(double);
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(host_out, s->st[s->cur[c]][c], b, hipMemcpyDeviceToHost) != hipSuccess)
+    return BG_STATUS_DEVICE_ERROR;
+  if (products) *products = s->products[c];
+  return BG_STATUS_SUCCESS;
+}
+
+bg_status_t bs_fill_factor(unsigned long long seed, int c, long long j, int n, double* out,
+                           void* stream) {
+  if (n < 1 || n > 4096 || c < 0 || j < 0 || !out) return BG_STATUS_INVALID_VALUE;
+  return bg::launch_fill_one(out, n, c, j, std::sqrt(3.0 / (double)n), seed, (hipStream_t)stream) ==
+                 hipSuccess
+             ? BG_STATUS_SUCCESS
+             : BG_STATUS_DEVICE_ERROR;
+}
+
+bg_status_t bs_simulate(int num_clients, int n_requests, const double* arrival_s,
+                        const int* client, const int* length, double tick_s, double* out_start,
+                        double* out_finish, long long* out_ticks) {
+  if (num_clients <= 0 || !(tick_s > 0.0) ||
+      !bs::valid_schedule(num_clients, n_requests, arrival_s, client, length) ||
+      (n_requests > 0 && (!out_start || !out_finish)))
+    return BG_STATUS_INVALID_VALUE;
+  bs::Scheduler sc;
+  sc.init(num_clients, n_requests, arrival_s, client, length, out_start, out_finish);
+  double now = 0.0;
+  long long ticks = 0;
+  while (!sc.done()) {
+    sc.admit(now);
+    if (sc.begin_tick(now) == 0) {
+      now = sc.next_arrival();
+      continue;
+    }
+    now += tick_s;
+    sc.end_tick(now);
+    ++ticks;
+  }
+  if (out_ticks) *out_ticks = ticks;
+  return BG_STATUS_SUCCESS;
+}
+
+bg_status_t bs_run_schedule(bs_server_t s, int n_requests, const double* arrival_s,
+                            const int* client, const int* length, double* out_start,
+                            double* out_finish, long long* out_ticks) {
+  if (!valid(s)) return BG_STATUS_INVALID_HANDLE;
+  if (!bs::valid_schedule(s->nc, n_requests, arrival_s, client, length) ||
+      (n_requests > 0 && (!out_start || !out_finish)))
+    return BG_STATUS_INVALID_VALUE;
+  void* sv = nullptr;
+  bg_get_stream(s->h, &sv);
+  const hipStream_t stream = (hipStream_t)sv;
+  bs::Scheduler sc;
+  sc.init(s->nc, n_requests, arrival_s, client, length, out_start, out_finish);
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  auto now = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
+  std::vector<int> order;
+  long long ticks = 0;
+  while (!sc.done()) {
+    sc.admit(now());
+    const int nb = sc.begin_tick(now());
+    if (nb == 0) {
+      const double t_next = sc.next_arrival();
+      while (now() < t_next) std::this_thread::yield();
+      continue;
+    }
+    // factor jobs, and the clients grouped by size (one launch per size)
+    order = sc.batch;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return s->sizes[a] < s->sizes[b]; });
+    int max_n = 0;
+    for (int i = 0; i < nb; ++i) {
+      const int c = order[i];
+      s->h_jobs[i] = bg::FillJob{s->fac[c], s->products[c], s->sizes[c], c, s->scale[c]};
+      s->h_ptrs[i] = s->fac[c];
+      s->h_ptrs[nb + i] = s->st[s->cur[c]][c];
+      s->h_ptrs[2 * nb + i] = s->st[s->cur[c] ^ 1][c];
+      if (s->sizes[c] > max_n) max_n = s->sizes[c];
+    }
+    if (hipMemcpyAsync(s->d_jobs, s->h_jobs, nb * sizeof(bg::FillJob), hipMemcpyHostToDevice,
+                       stream) != hipSuccess ||
+        hipMemcpyAsync((void*)s->d_ptrs, (const void*)s->h_ptrs, 3 * nb * sizeof(double*),
+                       hipMemcpyHostToDevice, stream) != hipSuccess ||
+        bg::launch_fill_factors(s->d_jobs, nb, max_n, s->seed, stream) != hipSuccess)
+      return BG_STATUS_DEVICE_ERROR;
+    for (int g0 = 0; g0 < nb;) {
+      int g1 = g0;
+      const int n = s->sizes[order[g0]];
+      while (g1 < nb && s->sizes[order[g1]] == n) ++g1;
+      const bg_status_t st = bg_dgemm_batched(
+          s->h, 'N', 'N', n, n, n, 1.0, s->d_ptrs + g0, n, s->d_ptrs + nb + g0, n, 0.0,
+          (double* const*)(s->d_ptrs + 2 * nb + g0), n, g1 - g0);
+      if (st != BG_STATUS_SUCCESS) return st;
+      g0 = g1;
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) return BG_STATUS_DEVICE_ERROR;
+    for (int c : sc.batch) {
+      s->cur[c] ^= 1;
+      ++s->products[c];
+    }
+    sc.end_tick(now());
+    ++ticks;
+  }
+  if (out_ticks) *out_ticks = ticks;
+  return BG_STATUS_SUCCESS;
+}
+
+}  // extern "C"

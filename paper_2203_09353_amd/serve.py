@@ -1,0 +1,164 @@
+"""Python binding of the request loop (include/bgserve.h) and the request
+workload of the serving benchmark.
+
+Argument marshalling only: the scheduler and the tick loop run in C++ inside
+libbgemm.so, the factors are generated and multiplied by its kernels.
+
+Workload (seeded, synthetic; the paper's procedures apply random local gates
+and GEMMs to their states, Section III): ``clients`` clients, client c of size
+2^k_c with k_c uniform in 5..9; requests arrive as a Poisson process of rate
+``rate`` per second over ``duration`` seconds, each for a uniformly chosen
+client, with a chain length uniform in 1..16.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import bgemm, inputs
+
+_set = False
+
+
+def _lib():
+    global _set
+    L = bgemm.lib()
+    if not _set:
+        vp, i, d, u64, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_ulonglong, ctypes.c_longlong
+        L.bs_create.restype = i
+        L.bs_create.argtypes = [vp, i, vp, u64, u64, ctypes.POINTER(vp)]
+        L.bs_destroy.restype = i
+        L.bs_destroy.argtypes = [vp]
+        L.bs_bytes_needed.restype = u64
+        L.bs_bytes_needed.argtypes = [i, vp]
+        L.bs_reset.restype = i
+        L.bs_reset.argtypes = [vp]
+        L.bs_run_schedule.restype = i
+        L.bs_run_schedule.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(ll)]
+        L.bs_state.restype = i
+        L.bs_state.argtypes = [vp, i, vp, ctypes.POINTER(ll)]
+        L.bs_fill_factor.restype = i
+        L.bs_fill_factor.argtypes = [u64, i, ll, i, vp, vp]
+        L.bs_simulate.restype = i
+        L.bs_simulate.argtypes = [i, i, vp, vp, vp, d, vp, vp, ctypes.POINTER(ll)]
+        _set = True
+    return L
+
+
+def _arr(x, dtype):
+    return np.ascontiguousarray(np.asarray(x, dtype=dtype))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+
+
+def bytes_needed(sizes) -> int:
+    s = _arr(sizes, np.int32)
+    return int(_lib().bs_bytes_needed(len(s), _ptr(s)))
+
+
+def simulate(num_clients, arrivals, clients, lengths, tick_s):
+    """Host-only replay of the scheduler on a virtual clock (no device):
+    returns (start, finish, ticks)."""
+    a, c, l = _arr(arrivals, np.float64), _arr(clients, np.int32), _arr(lengths, np.int32)
+    n = len(a)
+    st, fi = np.zeros(n), np.zeros(n)
+    ticks = ctypes.c_longlong()
+    r = _lib().bs_simulate(num_clients, n, _ptr(a), _ptr(c), _ptr(l), float(tick_s), _ptr(st),
+                           _ptr(fi), ctypes.byref(ticks))
+    if r != 0:
+        raise bgemm.BgemmError("bs_simulate", r)
+    return st, fi, ticks.value
+
+
+def fill_factor(seed, client, j, n, out: torch.Tensor):
+    """Factor j of a client into a CUDA float64 tensor of n * n elements."""
+    assert out.is_cuda and out.dtype == torch.float64 and out.numel() == n * n
+    r = _lib().bs_fill_factor(seed, client, j, n, out.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+    if r != 0:
+        raise bgemm.BgemmError("bs_fill_factor", r)
+
+
+class Server:
+    """Request loop on a bgemm handle (its device, torch's current stream)."""
+
+    def __init__(self, handle: bgemm.Handle, sizes, seed: int, budget: int = 0):
+        self.L = _lib()
+        self.handle = handle
+        self.sizes = _arr(sizes, np.int32)
+        handle._sync_stream()
+        out = ctypes.c_void_p()
+        r = self.L.bs_create(handle._h, len(self.sizes), _ptr(self.sizes), seed, budget,
+                             ctypes.byref(out))
+        if r != 0:
+            raise bgemm.BgemmError("bs_create", r)
+        self._s = out
+
+    def close(self):
+        if getattr(self, "_s", None):
+            self.L.bs_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        self.handle._sync_stream()
+        r = self.L.bs_reset(self._s)
+        if r != 0:
+            raise bgemm.BgemmError("bs_reset", r)
+
+    def run(self, arrivals, clients, lengths):
+        """Runs an open-loop schedule; returns (start, finish, ticks), times in
+        seconds from the start of the call."""
+        a, c, l = _arr(arrivals, np.float64), _arr(clients, np.int32), _arr(lengths, np.int32)
+        n = len(a)
+        st, fi = np.zeros(n), np.zeros(n)
+        ticks = ctypes.c_longlong()
+        self.handle._sync_stream()
+        r = self.L.bs_run_schedule(self._s, n, _ptr(a), _ptr(c), _ptr(l), _ptr(st), _ptr(fi),
+                                   ctypes.byref(ticks))
+        if r != 0:
+            raise bgemm.BgemmError("bs_run_schedule", r)
+        return st, fi, ticks.value
+
+    def state(self, client):
+        """(state as an ordinary n x n array, products applied so far)."""
+        n = int(self.sizes[client])
+        buf = np.empty(n * n)
+        prods = ctypes.c_longlong()
+        r = self.L.bs_state(self._s, client, _ptr(buf), ctypes.byref(prods))
+        if r != 0:
+            raise bgemm.BgemmError("bs_state", r)
+        return buf.reshape(n, n).T.copy(), prods.value
+
+
+def client_sizes(seed: int, clients: int, kmin: int = 5, kmax: int = 9):
+    u = inputs.uniform_flat(seed, 10, 0, clients).numpy()
+    k = np.clip(np.floor((u + 1.0) * 0.5 * (kmax - kmin + 1)), 0, kmax - kmin).astype(int) + kmin
+    return (2 ** k).astype(np.int32)
+
+
+def requests(seed: int, clients: int, rate: float, duration: float, max_len: int = 16):
+    """Poisson arrivals (exponential gaps from the seeded generator), a client
+    and a chain length per request: (arrivals, clients, lengths)."""
+    n = max(1, int(math.ceil(rate * duration * 1.5)) + 16)
+    u = (inputs.uniform_flat(seed, 11, 0, n).numpy() + 1.0) * 0.5     # [0, 1)
+    gaps = -np.log1p(-u) / rate
+    t = np.cumsum(gaps)
+    keep = t < duration
+    t = t[keep]
+    m = len(t)
+    uc = (inputs.uniform_flat(seed, 12, 0, m).numpy() + 1.0) * 0.5
+    ul = (inputs.uniform_flat(seed, 13, 0, m).numpy() + 1.0) * 0.5
+    cl = np.minimum((uc * clients).astype(np.int32), clients - 1)
+    ln = np.minimum((ul * max_len).astype(np.int32), max_len - 1) + 1
+    return t, cl, ln

@@ -12,18 +12,32 @@ from paper_2203_09353_amd import bgemm
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared_symbols():
-    with open(os.path.join(ROOT, "include", "bgemm.h")) as f:
+def _declared_symbols(header, prefix):
+    with open(os.path.join(ROOT, "include", header)) as f:
         text = f.read()
-    return set(re.findall(r"\b(bg_[a-z_]+)\s*\(", text))
+    return set(re.findall(r"\b(%s_[a-z_]+)\s*\(" % prefix, text))
 
 
 def test_library_exports_every_declared_symbol():
     L = bgemm.lib()
-    declared = _declared_symbols()
+    declared = _declared_symbols("bgemm.h", "bg")
     assert declared == set(bgemm.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
+
+
+def test_library_exports_the_request_loop():
+    from paper_2203_09353_amd import serve
+    L = serve._lib()
+    declared = _declared_symbols("bgserve.h", "bs")
+    assert declared == {"bs_create", "bs_destroy", "bs_bytes_needed", "bs_reset",
+                        "bs_run_schedule", "bs_state", "bs_fill_factor", "bs_simulate"}
+    for name in declared:
+        assert hasattr(L, name), name
+    # host-side argument checks need no device
+    assert L.bs_destroy(None) == 5
+    assert L.bs_reset(None) == 5
+    assert L.bs_fill_factor(1, 0, 0, 0, None, None) == 1
 
 
 def test_version_and_status_strings():
