@@ -9,19 +9,21 @@ namespace bg {
 
 // Tile shapes.  A "size class" is one tile configuration of the MFMA tile
 // kernel: C tile BM x BN per workgroup, contraction step BK per LDS stage,
-// each wave computing a WM x WN sub-tile with 16x16x4 FP64 MFMAs.
+// each wave computing a WM x WN sub-tile with 4x4x4 FP64 MFMAs (the exact
+// shapes come from the BG_CFG* macros, i.e. the tune cache).
 enum TileClass : int {
-  TC_32 = 0,     // 32x32 tile, one wave           (tiny matrices)
-  TC_64 = 1,     // 64x64 tile, four 32x32 waves   (small matrices)
-  TC_128 = 2,    // 128x128 tile, four 64x64 waves (large matrices)
+  TC_32 = 0,     // 32 x 32 tile         (tiny matrices)
+  TC_64 = 1,     // 64 x 64 tile         (small matrices, short batches)
+  TC_128 = 2,    // 128 x 64 tile        (large matrices)
   TC_COUNT = 3
 };
 
 struct TileShape { int bm, bn, bk, threads; };
 TileShape tile_shape(TileClass c);
 
-// Picks the tile class for a uniform batch; `force` >= 0 overrides.
-TileClass pick_uniform_class(int m, int n, int k, int force);
+// Picks the tile class for a uniform batch of `batch` instances on a device
+// of `num_cus` compute units; `force` >= 0 overrides.
+TileClass pick_uniform_class(int m, int n, int k, int batch, int num_cus, int force);
 
 struct UniformArgs {
   bool ta, tb;

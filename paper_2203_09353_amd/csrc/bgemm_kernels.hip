@@ -716,12 +716,18 @@ TileShape tile_shape(TileClass c) {
   }
 }
 
-TileClass pick_uniform_class(int m, int n, int k, int force) {
+TileClass pick_uniform_class(int m, int n, int k, int batch, int num_cus, int force) {
   (void)k;
   if (force >= 0 && force < TC_COUNT) return (TileClass)force;
   const int mx = m > n ? m : n;
   if (mx <= 32) return TC_32;
   if (mx <= 64) return TC_64;
+  // A batch too small to give every CU two 128 x 64 tiles is spread over
+  // twice as many 64 x 64 tiles instead (a short batch is latency-bound:
+  // more, shorter tiles finish sooner).
+  const int64_t tiles128 = (int64_t)((m + Cfg128::BM - 1) / Cfg128::BM) *
+                           ((n + Cfg128::BN - 1) / Cfg128::BN) * batch;
+  if (tiles128 < 2 * (int64_t)num_cus) return TC_64;
   return TC_128;
 }
 

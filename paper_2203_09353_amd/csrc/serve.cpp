@@ -44,9 +44,14 @@ struct Scheduler {
     while (next < nreq && arrival[next] <= now) queue[client[next]].push_back(next++);
   }
   // Starts the oldest queued request of every idle client; the tick serves
-  // every client with an active request.
+  // every client with an active request.  A request whose last product is in
+  // this tick is listed in `last` and leaves its client idle for the next
+  // tick (whose product on the same state is ordered after this one on the
+  // device); it counts as finished when the tick completes.
+  std::vector<int> last;
   int begin_tick(double now) {
     batch.clear();
+    last.clear();
     for (int c = 0; c < nc; ++c) {
       if (active[c] < 0 && !queue[c].empty()) {
         const int r = queue[c].front();
@@ -55,17 +60,19 @@ struct Scheduler {
         remaining[c] = length[r];
         start[r] = now;
       }
-      if (active[c] >= 0) batch.push_back(c);
+      if (active[c] >= 0) {
+        batch.push_back(c);
+        if (--remaining[c] == 0) {
+          last.push_back(active[c]);
+          active[c] = -1;
+        }
+      }
     }
     return (int)batch.size();
   }
-  void end_tick(double now) {
-    for (int c : batch)
-      if (--remaining[c] == 0) {
-        finish[active[c]] = now;
-        active[c] = -1;
-        ++finished;
-      }
+  void complete(const std::vector<int>& fin, double now) {
+    for (int r : fin) finish[r] = now;
+    finished += (int)fin.size();
   }
   bool done() const { return finished == nreq; }
   double next_arrival() const {
@@ -96,10 +103,14 @@ struct bs_server {
   std::vector<double*> fac;
   std::vector<int> cur;
   std::vector<long long> products;
-  bg::FillJob* d_jobs;
-  bg::FillJob* h_jobs;            // pinned
-  const double** d_ptrs;
-  const double** h_ptrs;          // pinned
+  // two sets of job / pointer arrays, so one tick can be prepared while the
+  // previous one runs
+  bg::FillJob* d_jobs[2];
+  bg::FillJob* h_jobs[2];         // pinned
+  const double** d_ptrs[2];
+  const double** h_ptrs[2];       // pinned
+  hipEvent_t ev[2];
+  hipEvent_t ev0;
 };
 
 static const unsigned kServerMagic = 0x5E7BE5E7u;
@@ -111,10 +122,14 @@ static void free_all(bs_server* s) {
   for (int b = 0; b < 2; ++b)
     for (double* p : s->st[b]) if (p) (void)hipFree(p);
   for (double* p : s->fac) if (p) (void)hipFree(p);
-  if (s->d_jobs) (void)hipFree(s->d_jobs);
-  if (s->d_ptrs) (void)hipFree((void*)s->d_ptrs);
-  if (s->h_jobs) (void)hipHostFree(s->h_jobs);
-  if (s->h_ptrs) (void)hipHostFree((void*)s->h_ptrs);
+  for (int b = 0; b < 2; ++b) {
+    if (s->d_jobs[b]) (void)hipFree(s->d_jobs[b]);
+    if (s->d_ptrs[b]) (void)hipFree((void*)s->d_ptrs[b]);
+    if (s->h_jobs[b]) (void)hipHostFree(s->h_jobs[b]);
+    if (s->h_ptrs[b]) (void)hipHostFree((void*)s->h_ptrs[b]);
+    if (s->ev[b]) (void)hipEventDestroy(s->ev[b]);
+  }
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
 }
 
 static hipError_t set_identity(bs_server* s, hipStream_t stream) {
@@ -132,7 +147,7 @@ unsigned long long bs_bytes_needed(int num_clients, const int* sizes) {
   unsigned long long t = 0;
   for (int c = 0; c < num_clients; ++c)
     if (sizes[c] > 0) t += client_bytes(sizes[c]);
-  t += (unsigned long long)num_clients * (sizeof(bg::FillJob) + 3 * sizeof(double*));
+  t += 2ull * num_clients * (sizeof(bg::FillJob) + 3 * sizeof(double*));
   return t;
 }
 
@@ -164,10 +179,13 @@ bg_status_t bs_create(bg_handle_t h, int num_clients, const int* sizes, unsigned
     ok = hipMalloc(&s->st[0][c], b) == hipSuccess && hipMalloc(&s->st[1][c], b) == hipSuccess &&
          hipMalloc(&s->fac[c], b) == hipSuccess;
   }
-  ok = ok && hipMalloc(&s->d_jobs, num_clients * sizeof(bg::FillJob)) == hipSuccess &&
-       hipMalloc((void**)&s->d_ptrs, 3 * num_clients * sizeof(double*)) == hipSuccess &&
-       hipHostMalloc((void**)&s->h_jobs, num_clients * sizeof(bg::FillJob)) == hipSuccess &&
-       hipHostMalloc((void**)&s->h_ptrs, 3 * num_clients * sizeof(double*)) == hipSuccess;
+  for (int b = 0; b < 2 && ok; ++b)
+    ok = hipMalloc(&s->d_jobs[b], num_clients * sizeof(bg::FillJob)) == hipSuccess &&
+         hipMalloc((void**)&s->d_ptrs[b], 3 * num_clients * sizeof(double*)) == hipSuccess &&
+         hipHostMalloc((void**)&s->h_jobs[b], num_clients * sizeof(bg::FillJob)) == hipSuccess &&
+         hipHostMalloc((void**)&s->h_ptrs[b], 3 * num_clients * sizeof(double*)) == hipSuccess &&
+         hipEventCreate(&s->ev[b]) == hipSuccess;
+  ok = ok && hipEventCreate(&s->ev0) == hipSuccess;
   if (!ok) {
     free_all(s);
     s->magic = 0;
@@ -245,7 +263,7 @@ bg_status_t bs_simulate(int num_clients, int n_requests, const double* arrival_s
       continue;
     }
     now += tick_s;
-    sc.end_tick(now);
+    sc.complete(sc.last, now);
     ++ticks;
   }
   if (out_ticks) *out_ticks = ticks;
@@ -265,53 +283,91 @@ bg_status_t bs_run_schedule(bs_server_t s, int n_requests, const double* arrival
   bs::Scheduler sc;
   sc.init(s->nc, n_requests, arrival_s, client, length, out_start, out_finish);
   using clk = std::chrono::steady_clock;
+  // Up to two ticks in flight: the host prepares and launches tick t + 1
+  // while tick t runs.  A tick's completion time is read from its event
+  // relative to an event recorded when the call starts.
+  struct InFlight {
+    int set;
+    std::vector<int> fin;
+  };
+  std::deque<InFlight> flight;
+  if (hipStreamSynchronize(stream) != hipSuccess || hipEventRecord(s->ev0, stream) != hipSuccess)
+    return BG_STATUS_DEVICE_ERROR;
   const auto t0 = clk::now();
   auto now = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
+  auto retire = [&](bool wait) -> bool {
+    InFlight& f = flight.front();
+    const hipError_t q = wait ? hipEventSynchronize(s->ev[f.set]) : hipEventQuery(s->ev[f.set]);
+    if (q == hipErrorNotReady) return false;
+    if (q != hipSuccess) return false;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev0, s->ev[f.set]) != hipSuccess) ms = (float)(now() * 1e3);
+    sc.complete(f.fin, (double)ms * 1e-3);
+    flight.pop_front();
+    return true;
+  };
   std::vector<int> order;
   long long ticks = 0;
+  int set = 0;
   while (!sc.done()) {
+    while (!flight.empty() && retire(false)) {}
+    if (sc.done()) break;
+    if (flight.size() == 2) {
+      if (!retire(true)) return BG_STATUS_DEVICE_ERROR;
+      continue;
+    }
     sc.admit(now());
     const int nb = sc.begin_tick(now());
     if (nb == 0) {
+      if (!flight.empty()) {
+        if (!retire(true)) return BG_STATUS_DEVICE_ERROR;
+        continue;
+      }
       const double t_next = sc.next_arrival();
       while (now() < t_next) std::this_thread::yield();
       continue;
     }
-    // factor jobs, and the clients grouped by size (one launch per size)
+    // factor jobs, and the clients grouped by size
     order = sc.batch;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return s->sizes[a] < s->sizes[b]; });
-    int max_n = 0;
+    bg::FillJob* hj = s->h_jobs[set];
+    const double** hp = s->h_ptrs[set];
+    const double** dp = s->d_ptrs[set];
     for (int i = 0; i < nb; ++i) {
       const int c = order[i];
-      s->h_jobs[i] = bg::FillJob{s->fac[c], s->products[c], s->sizes[c], c, s->scale[c]};
-      s->h_ptrs[i] = s->fac[c];
-      s->h_ptrs[nb + i] = s->st[s->cur[c]][c];
-      s->h_ptrs[2 * nb + i] = s->st[s->cur[c] ^ 1][c];
-      if (s->sizes[c] > max_n) max_n = s->sizes[c];
+      hj[i] = bg::FillJob{s->fac[c], s->products[c], s->sizes[c], c, s->scale[c]};
+      hp[i] = s->fac[c];
+      hp[nb + i] = s->st[s->cur[c]][c];
+      hp[2 * nb + i] = s->st[s->cur[c] ^ 1][c];
     }
-    if (hipMemcpyAsync(s->d_jobs, s->h_jobs, nb * sizeof(bg::FillJob), hipMemcpyHostToDevice,
+    // the tick's arrays go up, all factors are generated in one launch, then
+    // one batched launch per distinct size, all on the handle's stream
+    int max_n = 0;
+    for (int i = 0; i < nb; ++i) max_n = std::max(max_n, s->sizes[order[i]]);
+    if (hipMemcpyAsync(s->d_jobs[set], hj, nb * sizeof(bg::FillJob), hipMemcpyHostToDevice,
                        stream) != hipSuccess ||
-        hipMemcpyAsync((void*)s->d_ptrs, (const void*)s->h_ptrs, 3 * nb * sizeof(double*),
+        hipMemcpyAsync((void*)dp, (const void*)hp, 3 * nb * sizeof(double*),
                        hipMemcpyHostToDevice, stream) != hipSuccess ||
-        bg::launch_fill_factors(s->d_jobs, nb, max_n, s->seed, stream) != hipSuccess)
+        bg::launch_fill_factors(s->d_jobs[set], nb, max_n, s->seed, stream) != hipSuccess)
       return BG_STATUS_DEVICE_ERROR;
     for (int g0 = 0; g0 < nb;) {
       int g1 = g0;
       const int n = s->sizes[order[g0]];
       while (g1 < nb && s->sizes[order[g1]] == n) ++g1;
-      const bg_status_t st = bg_dgemm_batched(
-          s->h, 'N', 'N', n, n, n, 1.0, s->d_ptrs + g0, n, s->d_ptrs + nb + g0, n, 0.0,
-          (double* const*)(s->d_ptrs + 2 * nb + g0), n, g1 - g0);
+      const bg_status_t st = bg_dgemm_batched(s->h, 'N', 'N', n, n, n, 1.0, dp + g0, n,
+                                              dp + nb + g0, n, 0.0,
+                                              (double* const*)(dp + 2 * nb + g0), n, g1 - g0);
       if (st != BG_STATUS_SUCCESS) return st;
       g0 = g1;
     }
-    if (hipStreamSynchronize(stream) != hipSuccess) return BG_STATUS_DEVICE_ERROR;
+    if (hipEventRecord(s->ev[set], stream) != hipSuccess) return BG_STATUS_DEVICE_ERROR;
     for (int c : sc.batch) {
       s->cur[c] ^= 1;
       ++s->products[c];
     }
-    sc.end_tick(now());
+    flight.push_back(InFlight{set, sc.last});
+    set ^= 1;
     ++ticks;
   }
   if (out_ticks) *out_ticks = ticks;

@@ -86,9 +86,9 @@ def test_workload_recipe():
 
 
 def test_bytes_needed():
-    # three n x n binary64 buffers per client, plus a 32-byte job and three
-    # 8-byte pointers
-    assert serve.bytes_needed([32, 64]) == 3 * 8 * (32 * 32 + 64 * 64) + 2 * (32 + 24)
+    # three n x n binary64 buffers per client, plus two sets (two ticks in
+    # flight) of a 32-byte job and three 8-byte pointers
+    assert serve.bytes_needed([32, 64]) == 3 * 8 * (32 * 32 + 64 * 64) + 2 * 2 * (32 + 24)
 
 
 def test_replay_pins():
