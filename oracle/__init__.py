@@ -65,6 +65,17 @@ def lib():
                                             _c_int_p, ctypes.c_double, _c_dbl_pp, _c_int_p,
                                             _c_dbl_pp, _c_int_p, ctypes.c_double, _c_dbl_pp,
                                             _c_int_p, ctypes.c_int, _c_int_p, ctypes.c_int]
+        _c_dbl_p = ctypes.POINTER(ctypes.c_double)
+        L.oracle_zgemm.restype = ctypes.c_int
+        L.oracle_zgemm.argtypes = [ctypes.c_char, ctypes.c_char, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, _c_dbl_p, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_int, _c_dbl_p, ctypes.c_void_p,
+                                   ctypes.c_int]
+        L.oracle_zgemm_batched.restype = ctypes.c_int
+        L.oracle_zgemm_batched.argtypes = [ctypes.c_char, ctypes.c_char, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, _c_dbl_p, _c_dbl_pp,
+                                           ctypes.c_int, _c_dbl_pp, ctypes.c_int, _c_dbl_p,
+                                           _c_dbl_pp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
         L.oracle_max_threads.argtypes = []
         _lib = L
@@ -149,3 +160,42 @@ def gemm_vbatched(transa, transb, ms, ns, ks, alpha, As, Bs, beta, Cs,
     if r != 0:
         raise ValueError("oracle_dgemm_vbatched: status %d" % r)
     return info
+
+
+def _zptr(a: np.ndarray) -> int:
+    assert a.dtype == np.complex128 and a.flags.c_contiguous
+    return a.ctypes.data
+
+
+def _pair(z):
+    z = complex(z)
+    return (ctypes.c_double * 2)(z.real, z.imag)
+
+
+def zgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:
+    """One complex instance on C-contiguous complex128 buffers (interleaved
+    real / imaginary binary64 pairs); C is updated in place.  Returns 0 or
+    -(argument number)."""
+    r = lib().oracle_zgemm(_ch(transa), _ch(transb), m, n, k, _pair(alpha), _zptr(A), lda,
+                           _zptr(B), ldb, _pair(beta), _zptr(C), ldc)
+    if r == -100:
+        raise MemoryError("oracle_zgemm: allocation failed")
+    return r
+
+
+def zgemm_batched(transa, transb, m, n, k, alpha, A, B, beta, C, nthreads=0):
+    """Uniform complex batch: A, B, C are (batch, cols, ld) complex128 arrays
+    (ld in complex elements); C is updated in place."""
+    As, Bs, Cs = _split(A), _split(B), _split(C)
+    batch = len(Cs)
+    assert len(As) == batch and len(Bs) == batch
+    ta, tb = transa in "TtCc", transb in "TtCc"
+    lda = As[0].shape[-1] if batch else max(1, k if ta else m)
+    ldb = Bs[0].shape[-1] if batch else max(1, n if tb else k)
+    ldc = Cs[0].shape[-1] if batch else max(1, m)
+    arr = lambda ms: (ctypes.c_void_p * len(ms))(*[_zptr(a) for a in ms])
+    r = lib().oracle_zgemm_batched(_ch(transa), _ch(transb), m, n, k, _pair(alpha), arr(As),
+                                   lda, arr(Bs), ldb, _pair(beta), arr(Cs), ldc, batch,
+                                   int(nthreads))
+    if r != 0:
+        raise ValueError("oracle_zgemm_batched: info %d" % r)

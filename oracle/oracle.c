@@ -180,3 +180,114 @@ int oracle_dgemm_vbatched(char transa, char transb, const int *m, const int *n,
     }
     return failed ? -100 : 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Complex instances (the paper's matrices are complex, Section II, Eq. 1).
+ * Elements are interleaved (real, imaginary) binary64 pairs; element (r, c)
+ * of a matrix with leading dimension ld (in complex elements) has its real
+ * part at 2 (r + c ld) and its imaginary part right after.  op(X) = X for
+ * 'N', X^T for 'T', the conjugate transpose X^H for 'C'.  alpha and beta are
+ * (real, imaginary) pairs.
+ *
+ * Arithmetic, in the plain order: the complex product is the real product of
+ * the embedded operands, so each output part is a real dot product of length
+ * 2k whose terms are taken for p = 0, 1, ..., k-1 in turn:
+ *     acc_re = acc_re + a_re * b_re;  acc_re = acc_re + (-a_im) * b_im;
+ *     acc_im = acc_im + a_im * b_re;  acc_im = acc_im + a_re * b_im;
+ * (a = opA(r, p), b = opB(p, j); each product and each add rounded).  Then
+ * x = alpha acc and y = beta C as (p_re q_re - p_im q_im, p_re q_im + p_im q_re)
+ * with every product and the add / subtract rounded, and C = x + y part by
+ * part.  Scalar rules (BLAS): beta == 0 never reads C; alpha == 0 or k == 0
+ * never reads A or B and gives C = beta C (beta == 1 leaves C untouched).
+ * Argument numbers as for the real call (1 transa, 2 transb, 3 m, 4 n, 5 k,
+ * 8 lda, 10 ldb, 13 ldc); 'C' counts as a transpose for the ld rules.
+ * ------------------------------------------------------------------------ */
+static int ztrans_code(char t)
+{
+    if (t == 'N' || t == 'n') return 0;
+    if (t == 'T' || t == 't') return 1;
+    if (t == 'C' || t == 'c') return 2;
+    return -1;
+}
+
+int oracle_zgemm(char transa, char transb, int m, int n, int k, const double *alpha,
+                 const double *A, int lda, const double *B, int ldb,
+                 const double *beta, double *C, int ldc)
+{
+    int info = oracle_check_args(transa, transb, m, n, k, lda, ldb, ldc);
+    if (info != 0) return info;
+    if (m == 0 || n == 0) return 0;
+    int ta = ztrans_code(transa), tb = ztrans_code(transb);
+    int64_t slda = lda, sldb = ldb, sldc = ldc;
+    const double ar_ = alpha[0], ai_ = alpha[1], br_ = beta[0], bi_ = beta[1];
+    int alpha_zero = (ar_ == 0.0 && ai_ == 0.0);
+    int beta_zero = (br_ == 0.0 && bi_ == 0.0);
+    int beta_one = (br_ == 1.0 && bi_ == 0.0);
+    int use_product = !(alpha_zero || k == 0);
+
+    double *acc = (double *)malloc(sizeof(double) * 2 * (size_t)m);
+    if (!acc) return -100;
+    for (int j = 0; j < n; ++j) {
+        double *cj = C + 2 * (int64_t)j * sldc;
+        if (use_product) {
+            for (int r = 0; r < 2 * m; ++r) acc[r] = 0.0;
+            for (int p = 0; p < k; p++) {
+                const double *bp = tb ? B + 2 * ((int64_t)j + (int64_t)p * sldb)
+                                      : B + 2 * ((int64_t)p + (int64_t)j * sldb);
+                double bre = bp[0], bim = tb == 2 ? -bp[1] : bp[1];
+                for (int r = 0; r < m; ++r) {
+                    const double *ap = ta ? A + 2 * ((int64_t)p + (int64_t)r * slda)
+                                          : A + 2 * ((int64_t)r + (int64_t)p * slda);
+                    double are = ap[0], aim = ta == 2 ? -ap[1] : ap[1];
+                    double t;
+                    t = are * bre;    acc[2 * r] = acc[2 * r] + t;
+                    t = (-aim) * bim; acc[2 * r] = acc[2 * r] + t;
+                    t = aim * bre;    acc[2 * r + 1] = acc[2 * r + 1] + t;
+                    t = are * bim;    acc[2 * r + 1] = acc[2 * r + 1] + t;
+                }
+            }
+        }
+        for (int r = 0; r < m; ++r) {
+            double *c = cj + 2 * r;
+            if (!use_product) {
+                if (beta_zero) { c[0] = 0.0; c[1] = 0.0; }
+                else if (!beta_one) {
+                    double yr = br_ * c[0] - bi_ * c[1];
+                    double yi = br_ * c[1] + bi_ * c[0];
+                    c[0] = yr; c[1] = yi;
+                }
+                continue;
+            }
+            double xr = ar_ * acc[2 * r] - ai_ * acc[2 * r + 1];
+            double xi = ar_ * acc[2 * r + 1] + ai_ * acc[2 * r];
+            if (beta_zero) { c[0] = xr; c[1] = xi; continue; }
+            double yr = br_ * c[0] - bi_ * c[1];
+            double yi = br_ * c[1] + bi_ * c[0];
+            c[0] = xr + yr;
+            c[1] = xi + yi;
+        }
+    }
+    free(acc);
+    return 0;
+}
+
+int oracle_zgemm_batched(char transa, char transb, int m, int n, int k,
+                         const double *alpha, const double *const *A, int lda,
+                         const double *const *B, int ldb, const double *beta,
+                         double *const *C, int ldc, int batch, int nthreads)
+{
+    int info = oracle_check_args(transa, transb, m, n, k, lda, ldb, ldc);
+    if (info != 0) return info;
+    if (ztrans_code(transa) < 0) return -1;
+    if (ztrans_code(transb) < 0) return -2;
+    if (batch < 0) return -14;
+    int failed = 0;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : failed)
+    for (int i = 0; i < batch; ++i) {
+        int r = oracle_zgemm(transa, transb, m, n, k, alpha, A[i], lda, B[i], ldb,
+                             beta, C[i], ldc);
+        if (r != 0) failed = 1;
+    }
+    return failed ? -100 : 0;
+}
