@@ -165,6 +165,21 @@ bg_status_t bg_gemm_batched_mode(bg_handle_t h, int mode, int slices, char trans
                                  const double* const* dB, int ldb, double beta,
                                  double* const* dC, int ldc, int batch);
 
+/* Complex uniform batch (the paper's matrices are complex, Section II, Eq. 1):
+ * C_i <- alpha op(A_i) op(B_i) + beta C_i with op(X) = X ('N'), X^T ('T') or
+ * the conjugate transpose X^H ('C').  Elements are interleaved (real,
+ * imaginary) binary64 pairs (the layout of C99 double complex); leading
+ * dimensions count complex elements; alpha and beta point to host (real,
+ * imaginary) pairs.  Argument rules, numbering, quick returns and scalar
+ * rules follow bg_dgemm_batched (alpha == 0 means both parts zero; beta == 1
+ * means 1 + 0i); a NULL alpha or beta records argument 6 or 11.  Operands
+ * need 8-byte alignment. */
+bg_status_t bg_zgemm_batched(bg_handle_t h, char transa, char transb,
+                             int m, int n, int k, const double* alpha,
+                             const double* const* dA, int lda,
+                             const double* const* dB, int ldb, const double* beta,
+                             double* const* dC, int ldc, int batch);
+
 /* Overrides the size class chosen for uniform batches (-1 = automatic;
  * 0 = 32x32 tiles, 1 = 64x64, 2 = 128x128).  For tuning and tests. */
 bg_status_t bg_set_uniform_class(bg_handle_t h, int cls);

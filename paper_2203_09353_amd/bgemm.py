@@ -27,7 +27,8 @@ STATUS = {0: "SUCCESS", 1: "INVALID_VALUE", 2: "NOT_SUPPORTED", 3: "DEVICE_ERROR
 EXPORTS = ["bg_version", "bg_status_string", "bg_create", "bg_destroy", "bg_set_stream",
            "bg_get_stream", "bg_set_workspace", "bg_workspace_bytes_needed",
            "bg_last_invalid_arg", "bg_check_batched_args", "bg_dgemm_batched",
-           "bg_dgemm_vbatched", "bg_set_uniform_class", "bg_gemm_batched_mode"]
+           "bg_dgemm_vbatched", "bg_set_uniform_class", "bg_gemm_batched_mode",
+           "bg_zgemm_batched"]
 
 # bg_mode_t
 MODE_FP64, MODE_FP32, MODE_BF16, MODE_EMU = 0, 1, 2, 3
@@ -83,6 +84,9 @@ def lib(path: str | None = None):
     L.bg_dgemm_vbatched.argtypes = [vp, c, c, vp, vp, vp, d, vp, vp, vp, vp, d, vp, vp, i, vp]
     L.bg_set_uniform_class.restype = i
     L.bg_set_uniform_class.argtypes = [vp, i]
+    dp2 = ctypes.POINTER(ctypes.c_double)
+    L.bg_zgemm_batched.restype = i
+    L.bg_zgemm_batched.argtypes = [vp, c, c, i, i, i, dp2, vp, i, vp, i, dp2, vp, i, i]
     L.bg_gemm_batched_mode.restype = i
     L.bg_gemm_batched_mode.argtypes = [vp, i, i, c, c, i, i, i, d, vp, i, vp, i, d, vp, i, i]
     _lib = L
@@ -103,10 +107,10 @@ def pointer_array(x) -> torch.Tensor:
     """Device int64 tensor of per-instance data pointers for a (batch, cols,
     ld) tensor or a list of tensors (kept alive by the caller)."""
     if isinstance(x, torch.Tensor):
-        assert x.dim() == 3 and x.dtype == torch.float64 and x.is_cuda
+        assert x.dim() == 3 and x.dtype in (torch.float64, torch.complex128) and x.is_cuda
         nb = x.shape[0]
         base = x.data_ptr()
-        step = x.stride(0) * 8
+        step = x.stride(0) * x.element_size()
         return torch.arange(nb, dtype=torch.int64, device=x.device) * step + base
     ptrs = [t.data_ptr() for t in x]
     dev = x[0].device if len(x) else torch.device("cuda")
@@ -167,6 +171,30 @@ class Handle:
         return self._L.bg_gemm_batched_mode(self._h, int(mode), int(slices), _ch(transa),
                                             _ch(transb), m, n, k, float(alpha), pA, lda, pB, ldb,
                                             float(beta), pC, ldc, batch)
+
+    def zgemm_batched_raw(self, transa, transb, m, n, k, alpha, pA, lda, pB, ldb, beta, pC, ldc,
+                          batch) -> int:
+        self._sync_stream()
+        al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+        be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+        return self._L.bg_zgemm_batched(self._h, _ch(transa), _ch(transb), m, n, k, al, pA, lda,
+                                        pB, ldb, be, pC, ldc, batch)
+
+    def zbatched(self, A, B, C, m, n, k, alpha=1.0, beta=0.0, transa="N", transb="N",
+                 ptrs=None):
+        """Complex batch on stacked (batch, cols, ld) complex128 CUDA tensors
+        (or lists of (cols, ld) tensors); ld in complex elements."""
+        a0, b0, c0 = A[0], B[0], C[0]
+        lda, ldb, ldc = a0.shape[-1], b0.shape[-1], c0.shape[-1]
+        batch = C.shape[0] if isinstance(C, torch.Tensor) else len(C)
+        if ptrs is None:
+            ptrs = (pointer_array(A), pointer_array(B), pointer_array(C))
+        pA, pB, pC = ptrs
+        st = self.zgemm_batched_raw(transa, transb, m, n, k, alpha, pA.data_ptr(), lda,
+                                    pB.data_ptr(), ldb, beta, pC.data_ptr(), ldc, batch)
+        if st != 0:
+            raise BgemmError("bg_zgemm_batched", st, self.last_invalid_arg())
+        return ptrs
 
     def dgemm_vbatched_raw(self, transa, transb, pm, pn, pk, alpha, pA, plda, pB, pldb, beta, pC,
                            pldc, batch, pinfo) -> int:

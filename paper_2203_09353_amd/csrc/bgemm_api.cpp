@@ -233,6 +233,46 @@ bg_status_t bg_gemm_batched_mode(bg_handle_t h, int mode, int slices, char trans
   return e == hipSuccess ? BG_STATUS_SUCCESS : BG_STATUS_DEVICE_ERROR;
 }
 
+static int ztrans(char t) {
+  if (t == 'N' || t == 'n') return 0;
+  if (t == 'T' || t == 't') return 1;
+  if (t == 'C' || t == 'c') return 2;
+  return -1;
+}
+
+bg_status_t bg_zgemm_batched(bg_handle_t h, char transa, char transb, int m, int n, int k,
+                             const double* alpha, const double* const* dA, int lda,
+                             const double* const* dB, int ldb, const double* beta,
+                             double* const* dC, int ldc, int batch) {
+  if (!valid(h)) return BG_STATUS_INVALID_HANDLE;
+  int bad = bg_check_batched_args(transa, transb, m, n, k, dA, lda, dB, ldb, dC, ldc, batch);
+  if (!bad && !alpha) bad = 6;
+  if (!bad && !beta) bad = 11;
+  h->last_invalid_arg = bad;
+  if (bad) return BG_STATUS_INVALID_VALUE;
+  if (batch == 0 || m == 0 || n == 0) return BG_STATUS_SUCCESS;
+  const bool no_product = (alpha[0] == 0.0 && alpha[1] == 0.0) || k == 0;
+  const bool beta_one = beta[0] == 1.0 && beta[1] == 0.0;
+  if (no_product && beta_one) return BG_STATUS_SUCCESS;
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return BG_STATUS_DEVICE_ERROR;
+  hipError_t e;
+  if (no_product) {
+    e = bg::launch_zscale(beta, dC, ldc, m, n, batch, h->stream);
+  } else {
+    bg::ZUniformArgs a;
+    a.ta = ztrans(transa);
+    a.tb = ztrans(transb);
+    a.m = m; a.n = n; a.k = k;
+    a.alpha = alpha; a.beta = beta;
+    a.A = dA; a.lda = lda; a.B = dB; a.ldb = ldb; a.C = dC; a.ldc = ldc;
+    a.batch = batch;
+    e = bg::launch_zgemm(a, h->stream);
+    if (e == hipErrorInvalidValue) return BG_STATUS_NOT_SUPPORTED;
+  }
+  return e == hipSuccess ? BG_STATUS_SUCCESS : BG_STATUS_DEVICE_ERROR;
+}
+
 bg_status_t bg_dgemm_vbatched(bg_handle_t h, char transa, char transb, const int* d_m,
                               const int* d_n, const int* d_k, double alpha,
                               const double* const* dA, const int* d_lda, const double* const* dB,

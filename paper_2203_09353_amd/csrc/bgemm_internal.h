@@ -74,6 +74,23 @@ size_t vbatched_workspace_bytes(int batch);
 hipError_t launch_vbatched(const VbatchedArgs& a, const VbWorkspace& ws, int num_cus,
                            hipStream_t s);
 
+// Complex uniform batch (interleaved binary64 pairs; ld in complex elements;
+// op codes 0 N, 1 T, 2 C; alpha and beta point to host (re, im) pairs).
+struct ZUniformArgs {
+  int ta, tb;
+  int m, n, k;
+  const double* alpha;
+  const double* beta;
+  const double* const* A; int64_t lda;
+  const double* const* B; int64_t ldb;
+  double* const* C; int64_t ldc;
+  int batch;
+};
+hipError_t launch_zgemm(const ZUniformArgs& a, hipStream_t s);
+// C_i <- beta C_i for complex C (beta == 0 writes exact zeros, C not read).
+hipError_t launch_zscale(const double* beta, double* const* C, int64_t ldc, int m, int n,
+                         int batch, hipStream_t s);
+
 // Request loop: one generated factor (column-major n x n at `out`; factor j of
 // `client`, values scaled by `scale`).
 struct FillJob {
