@@ -3,6 +3,7 @@
     python bench.py [--steps K] [--warmup W] [--workload config2+vb]
     python bench.py --workload config4 [--modes fp64,fp32,bf16,emu3,emu6,emu7]
     python bench.py --workload config5 [--rates 1000,5000,20000,50000] [--duration 2]
+    python bench.py --workload gram15 [--steps K]
 
 A step is one pass over every part of the workload: the three uniform
 batches of 64^3, 256^3 and 512^3 (symmetric) instances through
@@ -21,6 +22,11 @@ clients with states of 2^k x 2^k (k uniform in 5..9), Poisson arrivals at each
 offered rate for ``--duration`` seconds, chains of 1..16 products whose
 factors are generated on the device; per rate the achieved GFLOP/s and the
 p50 / p99 request latency; ``value`` is the GFLOP/s at the highest rate.
+
+``--workload gram15`` times the complex batched GEMM on the paper's
+entanglement-entropy product: 10,000 Hermitian Gram products C = Psi Psi^H
+with Psi of 2^8 x 2^7 complex entries (S = 15 spins), binary64, counting
+8 m n k real flops per instance.
 """
 from __future__ import annotations
 
@@ -309,6 +315,92 @@ def serving_bench(args, h):
     print(json.dumps(out), flush=True)
 
 
+def gram_bench(args, h):
+    """The gram15 line: C_i = Psi_i Psi_i^H, Psi_i 256 x 128 complex."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2203_09353_amd import inputs, bgemm as bg
+
+    batch, rows, cols = 10_000, 256, 128
+    seed = 6
+    re = torch.empty(batch, cols, rows, dtype=torch.float64, device="cuda")
+    im = torch.empty_like(re)
+    for X, st in ((re, 0), (im, 1)):
+        flat = X.view(-1)
+        for off in range(0, flat.numel(), 1 << 26):
+            n = min(1 << 26, flat.numel() - off)
+            flat[off:off + n] = inputs.uniform_flat(seed, st, off, n, device="cuda")
+    Psi = torch.complex(re, im)
+    del re, im
+    C = torch.zeros(batch, rows, rows, dtype=torch.complex128, device="cuda")
+    perm = inputs.permutation(seed, 9, batch).cuda()
+    pP = bg.pointer_array(Psi)[perm]
+    pC = bg.pointer_array(C)[perm]
+
+    def launch():
+        st = h.zgemm_batched_raw("N", "C", rows, rows, cols, 1.0, pP.data_ptr(), rows,
+                                 pP.data_ptr(), rows, 0.0, pC.data_ptr(), rows, batch)
+        if st != 0:
+            raise RuntimeError("bg_zgemm_batched failed with status %d" % st)
+
+    launch()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i in inputs.permutation(11, 6, batch)[:max(1, args.check)].tolist():
+        P = Psi[i].cpu().numpy()[None]
+        ref = np.zeros((1, rows, rows), dtype=np.complex128)
+        oracle.zgemm_batched("N", "C", rows, rows, cols, 1.0, P, P, 0.0, ref)
+        got = C[i].cpu().numpy()
+        worst = max(worst, float(np.linalg.norm(got - ref[0]) / np.linalg.norm(ref[0])))
+    log("sampled parity (max rel Frobenius): %.3e" % worst)
+    for _ in range(args.warmup):
+        launch()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        launch()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    flops = 8.0 * rows * rows * cols * batch
+    tf = flops / (ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s", "frac": round(tf * 1e12 / PEAK_FP64, 4), "traffic": None,
+            "kernel": "k_zgemm (N, C) 256 x 256 x 128 complex"}
+    cpu = None
+    if not args.no_cpu:
+        log("timing the complex oracle on a sample")
+        threads = len(os.sched_getaffinity(0))
+        n = 1
+        while True:
+            P = Psi[:n].cpu().numpy()
+            ref = np.zeros((n, rows, rows), dtype=np.complex128)
+            t1 = time.perf_counter()
+            oracle.zgemm_batched("N", "C", rows, rows, cols, 1.0, P, P, 0.0, ref, nthreads=threads)
+            t = time.perf_counter() - t1
+            if t > args.cpu_seconds / 4 or n >= batch:
+                break
+            n = min(batch, n * 4)
+        cpu = {"value": round(8.0 * rows * rows * cols * n / t / 1e9, 3), "unit": "GFLOP/s",
+               "cores": threads, "kind": "oracle",
+               "sample": "first %d of %d instances, %.1f s" % (n, batch, t)}
+    out = {"metric": METRIC, "value": round(flops / (ms * 1e-3) / 1e9, 1), "unit": "GFLOP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "wall_ms_per_step": round(wall * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c128 (f64 pairs)",
+           "data": "synthetic (seeded counter-based uniform[-1,1) real and imaginary parts)",
+           "config": {"workload": "gram15", "instances": batch, "psi": [rows, cols],
+                      "op": "C = Psi Psi^H"},
+           "roofline": roof, "cpu_baseline": cpu, "parity_max_rel_fro": worst}
+    print(json.dumps(out), flush=True)
+
+
 def sampled_parity(h, parts, per_part, seed=11):
     """Runs one step and compares `per_part` seeded instances of every part
     with the CPU oracle (inputs copied to the host before the call)."""
@@ -433,6 +525,9 @@ def main():
     h = bgemm.Handle()
     if args.workload == "config5":
         serving_bench(args, h)
+        return
+    if args.workload == "gram15":
+        gram_bench(args, h)
         return
     log("building workload %s" % args.workload)
     t0 = time.perf_counter()
