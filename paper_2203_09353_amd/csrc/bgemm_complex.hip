@@ -9,13 +9,18 @@
 // so op(A) becomes a real (2m x 2k) matrix A'' of 2 x 2 blocks and op(B) a
 // real (2k x n) matrix B'' whose rows alternate real and imaginary parts.  The
 // expansion happens while a tile is written to LDS; the contraction is then a
-// real GEMM on the FP64 matrix cores (v_mfma_f64_16x16x4_f64), the same
-// number of multiply-adds as four real products.
+// real GEMM on the FP64 matrix cores, the same number of multiply-adds as four
+// real products.
 //
-// Within each 16-row block of A'' the rows are ordered (Re r0..r0+3,
-// Im r0..r0+3, Re r0+4..r0+7, Im r0+4..r0+7), so that the instruction's
-// result rows g, g+4, g+8, g+12 (lane group g) hold Re and Im of complex rows
-// r0+g and r0+4+g in one lane: the complex epilogue needs no lane exchange.
+// LDS holds, per step, two planes of the embedded A (the real-part rows
+// [Re a, -Im a] and the imaginary-part rows [Im a, Re a] over pairs of real
+// k) and B's embedded rows [Re b; Im b], all k-major.  One
+// v_mfma_f64_4x4x4_4b_f64 takes a 16-row slab of one plane (lane 16 s + r
+// holds row r at real k s) and four B columns replicated over the four blocks
+// (lane 16 s + 4 b + j holds column j), and yields a 16 x 4 block of the real
+// or of the imaginary parts of C (lane 16 i + 4 b + j holds row 4 b + i,
+// column j).  The two planes go to two accumulators, so the real and the
+// imaginary part of each C element sit in one lane for the complex epilogue.
 //
 // Tile: 64 x 64 complex C per workgroup, four waves of 32 x 32, eight complex
 // k per step (sixteen real k), double-buffered LDS, loads staged through
@@ -31,20 +36,19 @@ namespace cplx {
 #define AS_GLOBAL __attribute__((address_space(1)))
 #define AS_LDS __attribute__((address_space(3)))
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
 constexpr int BM = 64, BN = 64, BK = 8, NT = 256;
-constexpr int R2 = 2 * BM;          // real rows of an A'' tile
 constexpr int K2 = 2 * BK;          // real k of a step
-constexpr int SA = R2 + 16;         // LDS row strides (doubles): the four lane
-constexpr int SB = BN + 16;         // groups of a read fall in distinct bank halves
-constexpr int STAGE = K2 * SA + K2 * SB;
+// LDS row strides (doubles) of the A planes and of B's rows: the small pad keeps
+// a stage at 26 KB, so three workgroups fit a CU (measured 52.0 vs 43.5
+// TFLOP/s with a 16-double pad at two per CU)
+#ifndef BG_ZPAD
+#define BG_ZPAD 4
+#endif
+constexpr int SP = BM + BG_ZPAD;
+constexpr int SB = BN + BG_ZPAD;
+constexpr int PLANE = K2 * SP;
+constexpr int STAGE = 2 * PLANE + K2 * SB;
 constexpr int PER = BM * BK / NT;   // complex elements per thread per operand tile
-
-// real row of the A'' tile holding part `im` of complex row w (0..63)
-__device__ __forceinline__ int arow(int w, int im) {
-  return 16 * (w >> 3) + 8 * ((w >> 2) & 1) + 4 * im + (w & 3);
-}
 
 struct Z {
   double re, im;
@@ -89,19 +93,18 @@ struct Loader {
   }
 
   __device__ __forceinline__ void store(AS_LDS double* st, int tid) const {
-    AS_LDS double* la = st;
-    AS_LDS double* lb = st + K2 * SA;
+    AS_LDS double* pre = st;              // rows [Re a, -Im a]
+    AS_LDS double* pim = st + PLANE;      // rows [Im a,  Re a]
+    AS_LDS double* lb = st + 2 * PLANE;
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
       const int e = tid + it * NT;
       const int w = TA == 0 ? e % BM : e / BK;
       const int q = TA == 0 ? e / BM : e % BK;
-      const int rr = arow(w, 0), ri = arow(w, 1);
-      // 2 x 2 block [[re, -im], [im, re]] at real rows (rr, ri), real k (2q, 2q+1)
-      la[(2 * q) * SA + rr] = a[it].re;
-      la[(2 * q) * SA + ri] = a[it].im;
-      la[(2 * q + 1) * SA + rr] = -a[it].im;
-      la[(2 * q + 1) * SA + ri] = a[it].re;
+      pre[(2 * q) * SP + w] = a[it].re;
+      pre[(2 * q + 1) * SP + w] = -a[it].im;
+      pim[(2 * q) * SP + w] = a[it].im;
+      pim[(2 * q + 1) * SP + w] = a[it].re;
       const int q2 = TB == 0 ? e % BK : e / BN;
       const int c2 = TB == 0 ? e / BK : e % BN;
       lb[(2 * q2) * SB + c2] = b[it].re;
@@ -132,15 +135,19 @@ __global__ __launch_bounds__(NT) void k_zgemm(int M, int N, int K, double ar, do
   AS_GLOBAL double* C = (AS_GLOBAL double*)Cp[inst];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave & 1) * 64;        // wave's first real row of A'' (32 complex rows)
+  const int wr = (wave & 1) * 32;        // wave's first complex row
   const int wc = (wave >> 1) * 32;       // wave's first column
-  const int li = lane & 15, lg = lane >> 4;
+  const int ls = lane >> 4;              // real k within an instruction
+  const int lr = lane & 15, lj = lane & 3;
 
-  f64x4 acc[4][2];
+  // acc[t][part][g]: slab t (16 rows), part (0 Re, 1 Im), column group g (4)
+  double acc[2][2][8];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int pt = 0; pt < 2; ++pt)
+#pragma unroll
+      for (int g = 0; g < 8; ++g) acc[t][pt][g] = 0.0;
 
   Loader<TA, TB> ld;
   const int nk = (K + BK - 1) / BK;
@@ -150,52 +157,57 @@ __global__ __launch_bounds__(NT) void k_zgemm(int M, int N, int K, double ar, do
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) ld.load(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid);
-    const AS_LDS double* la = lds + cur * STAGE;
-    const AS_LDS double* lb = la + K2 * SA;
+    const AS_LDS double* pl = lds + cur * STAGE;
+    const AS_LDS double* lb = pl + 2 * PLANE;
 #pragma unroll
     for (int kk = 0; kk < K2; kk += 4) {
-      double fa[4], fb[2];
+      double fp[2][2], fq[8];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) fa[i] = la[(kk + lg) * SA + wr + 16 * i + li];
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fb[j] = lb[(kk + lg) * SB + wc + 16 * j + li];
+        for (int pt = 0; pt < 2; ++pt)
+          fp[t][pt] = pl[pt * PLANE + (kk + ls) * SP + wr + 16 * t + lr];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int g = 0; g < 8; ++g) fq[g] = lb[(kk + ls) * SB + wc + 4 * g + lj];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int pt = 0; pt < 2; ++pt)
+#pragma unroll
+          for (int g = 0; g < 8; ++g)
+            acc[t][pt][g] =
+                __builtin_amdgcn_mfma_f64_4x4x4f64(fp[t][pt], fq[g], acc[t][pt][g], 0, 0, 0);
     }
     if (kt + 1 < nk) ld.store(lds + (cur ^ 1) * STAGE, tid);
     __syncthreads();
   }
 
-  // Epilogue: block (i, j), register v: real row wr + 16 i + lg + 4 v, column
-  // wc + 16 j + li; v = 0 / 1 are Re / Im of complex row (wr/2) + 8 i + lg,
-  // v = 2 / 3 of complex row (wr/2) + 8 i + 4 + lg.
+  // Epilogue: lane 16 i + 4 b + j holds row wr + 16 t + 4 b + i, column
+  // wc + 4 g + j of slab t, group g (real part in acc[t][0][g], imaginary in
+  // acc[t][1][g]).
   const bool read_c = !(br == 0.0 && bi == 0.0);
+  const int li = lane >> 4, lb4 = (lane >> 2) & 3;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int r = m0 + wr / 2 + 8 * i + 4 * h + lg;
-        const int c = n0 + wc + 16 * j + li;
-        if (r >= M || c >= N) continue;
-        const double sr = acc[i][j][2 * h], si = acc[i][j][2 * h + 1];
-        double xr = ar * sr - ai * si;
-        double xi = ar * si + ai * sr;
-        AS_GLOBAL double* dst = C + 2 * ((int64_t)r + (int64_t)c * ldc);
-        if (read_c) {
-          const double cr = dst[0], ci = dst[1];
-          const double yr = br * cr - bi * ci;
-          const double yi = br * ci + bi * cr;
-          xr = xr + yr;
-          xi = xi + yi;
-        }
-        dst[0] = xr;
-        dst[1] = xi;
+    for (int g = 0; g < 8; ++g) {
+      const int r = m0 + wr + 16 * t + 4 * lb4 + li;
+      const int c = n0 + wc + 4 * g + lj;
+      if (r >= M || c >= N) continue;
+      const double sr = acc[t][0][g], si = acc[t][1][g];
+      double xr = ar * sr - ai * si;
+      double xi = ar * si + ai * sr;
+      AS_GLOBAL double* dst = C + 2 * ((int64_t)r + (int64_t)c * ldc);
+      if (read_c) {
+        const double cr = dst[0], ci = dst[1];
+        const double yr = br * cr - bi * ci;
+        const double yi = br * ci + bi * cr;
+        xr = xr + yr;
+        xi = xi + yi;
       }
+      dst[0] = xr;
+      dst[1] = xi;
+    }
 }
 
 // C <- beta C (complex), exactly zero when beta == 0 (C not read).
