@@ -4,6 +4,7 @@
     python bench.py --workload config4 [--modes fp64,fp32,bf16,emu3,emu6,emu7]
     python bench.py --workload config5 [--rates 1000,5000,20000,50000] [--duration 2]
     python bench.py --workload gram15 [--steps K]
+    python bench.py --workload gate21 [--steps K]
 
 A step is one pass over every part of the workload: the three uniform
 batches of 64^3, 256^3 and 512^3 (symmetric) instances through
@@ -27,6 +28,10 @@ p50 / p99 request latency; ``value`` is the GFLOP/s at the highest rate.
 entanglement-entropy product: 10,000 Hermitian Gram products C = Psi Psi^H
 with Psi of 2^8 x 2^7 complex entries (S = 15 spins), binary64, counting
 8 m n k real flops per instance.
+
+``--workload gate21`` times the two-spin gate on 64 states of S = 21 spins
+(2^21 binary64 complex amplitudes each, 32 MiB), a new seeded site and gate
+per state; HBM-bound (each state read and written once per step).
 """
 from __future__ import annotations
 
@@ -401,6 +406,69 @@ def gram_bench(args, h):
     print(json.dumps(out), flush=True)
 
 
+def gate_bench(args, h):
+    """The gate21 line: in-place two-spin gates on 64 states of 2^21 amplitudes."""
+    import numpy as np
+    import torch
+    from oracle import gates as G
+    from paper_2203_09353_amd import inputs
+
+    S, batch = 21, 64
+    amps = 1 << S
+    psi = torch.empty(batch, amps, dtype=torch.complex128, device="cuda")
+    view = torch.view_as_real(psi).view(-1)
+    for off in range(0, view.numel(), 1 << 26):
+        n = min(1 << 26, view.numel() - off)
+        view[off:off + n] = inputs.uniform_flat(7, 0, off, n, device="cuda")
+    g = inputs.gaussian_flat(7, 2, 0, batch * 32).view(batch, 32).numpy()
+    U = np.stack([G.haar_unitary(g[i, :16], g[i, 16:]) for i in range(batch)])
+    Ud = torch.tensor(U).cuda()
+    u = (inputs.uniform_flat(7, 3, 0, batch).numpy() + 1.0) * 0.5
+    sites = torch.tensor(np.minimum((u * (S - 1)).astype(np.int32), S - 2)).cuda()
+    # parity: one state, one step, against the oracle
+    before = psi[5].cpu().numpy()
+    h.zgate2(S, sites, Ud, psi)
+    torch.cuda.synchronize()
+    ref = G.apply_gate(before, S, int(sites[5]), U[5])
+    parity = float(np.abs(psi[5].cpu().numpy() - ref).max())
+    for _ in range(args.warmup):
+        h.zgate2(S, sites, Ud, psi)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        h.zgate2(S, sites, Ud, psi)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    nbytes = 2.0 * 16 * amps * batch            # every amplitude read and written once
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": round(gbps * 1e9 / PEAK_HBM, 4), "traffic": None,
+            "kernel": "k_gate2 (64 states of 2^21 amplitudes)"}
+    cpu = None
+    if not args.no_cpu:
+        st = psi[0].cpu().numpy()
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 10.0):
+            st = G.apply_gate(st, S, int(sites[0]), U[0])
+            reps += 1
+        t = time.perf_counter() - t0
+        cpu = {"value": round(2.0 * 16 * amps * reps / t / 1e9, 3), "unit": "GB/s", "cores": 1,
+               "kind": "oracle", "sample": "%d gates on one 2^21-amplitude state, %.1f s" % (reps, t)}
+    out = {"metric": "two-spin gate GB/s on 2^21-amplitude states, % HBM roofline",
+           "value": round(gbps, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "c128 (f64 pairs)",
+           "data": "synthetic (seeded uniform amplitudes, Haar 4x4 unitaries, seeded sites)",
+           "config": {"workload": "gate21", "states": batch, "spins": S},
+           "roofline": roof, "cpu_baseline": cpu, "parity_max_abs": parity}
+    print(json.dumps(out), flush=True)
+
+
 def sampled_parity(h, parts, per_part, seed=11):
     """Runs one step and compares `per_part` seeded instances of every part
     with the CPU oracle (inputs copied to the host before the call)."""
@@ -528,6 +596,9 @@ def main():
         return
     if args.workload == "gram15":
         gram_bench(args, h)
+        return
+    if args.workload == "gate21":
+        gate_bench(args, h)
         return
     log("building workload %s" % args.workload)
     t0 = time.perf_counter()

@@ -180,6 +180,22 @@ bg_status_t bg_zgemm_batched(bg_handle_t h, char transa, char transb,
                              const double* const* dB, int ldb, const double* beta,
                              double* const* dC, int ldc, int batch);
 
+/* Two-spin gates on a batch of S-spin states (the paper's Monte Carlo step
+ * applies a local unitary to a random pair of neighbouring spins, Section
+ * III, Alg. 1; the paper gives no gate model, so any 4 x 4 complex matrix
+ * is accepted).  State i (dPsi[i], 2^S interleaved binary64 complex
+ * amplitudes, 16-byte alignment recommended) is updated in place: amplitude
+ * x has spin j in bit j of x, and for site s = d_site[i] the gate
+ * dU[i] (4 x 4 complex, column-major: element (q, q') at 2 (q + 4 q'))
+ * maps every quadruple of amplitudes that differ only in bits s and s + 1
+ * (local index q = b_s + 2 b_{s+1}) to U times itself.  d_site, dU, dPsi and
+ * d_info (nullable; 0 done, -3 for a site outside 0..S-2, that state left
+ * untouched) are device arrays of length batch.  Host errors: S outside
+ * 2..40 (argument 2), NULL arrays when batch > 0 (3, 4, 5), batch < 0 (6). */
+bg_status_t bg_zgate2_batched(bg_handle_t h, int S, const int* d_site,
+                              const double* const* dU, double* const* dPsi, int batch,
+                              int* d_info);
+
 /* Overrides the size class chosen for uniform batches (-1 = automatic;
  * 0 = 32x32 tiles, 1 = 64x64, 2 = 128x128).  For tuning and tests. */
 bg_status_t bg_set_uniform_class(bg_handle_t h, int cls);

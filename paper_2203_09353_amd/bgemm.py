@@ -28,7 +28,7 @@ EXPORTS = ["bg_version", "bg_status_string", "bg_create", "bg_destroy", "bg_set_
            "bg_get_stream", "bg_set_workspace", "bg_workspace_bytes_needed",
            "bg_last_invalid_arg", "bg_check_batched_args", "bg_dgemm_batched",
            "bg_dgemm_vbatched", "bg_set_uniform_class", "bg_gemm_batched_mode",
-           "bg_zgemm_batched"]
+           "bg_zgemm_batched", "bg_zgate2_batched"]
 
 # bg_mode_t
 MODE_FP64, MODE_FP32, MODE_BF16, MODE_EMU = 0, 1, 2, 3
@@ -87,6 +87,8 @@ def lib(path: str | None = None):
     dp2 = ctypes.POINTER(ctypes.c_double)
     L.bg_zgemm_batched.restype = i
     L.bg_zgemm_batched.argtypes = [vp, c, c, i, i, i, dp2, vp, i, vp, i, dp2, vp, i, i]
+    L.bg_zgate2_batched.restype = i
+    L.bg_zgate2_batched.argtypes = [vp, i, vp, vp, vp, i, vp]
     L.bg_gemm_batched_mode.restype = i
     L.bg_gemm_batched_mode.argtypes = [vp, i, i, c, c, i, i, i, d, vp, i, vp, i, d, vp, i, i]
     _lib = L
@@ -195,6 +197,26 @@ class Handle:
         if st != 0:
             raise BgemmError("bg_zgemm_batched", st, self.last_invalid_arg())
         return ptrs
+
+    def zgate2(self, S, sites, U, psi, info=None):
+        """Two-spin gates in place: sites a CUDA int32 tensor (batch,), U a
+        CUDA complex128 tensor (batch, 4, 4) of ordinary matrices, psi a CUDA
+        complex128 tensor (batch, 2^S).  Returns the info tensor."""
+        batch = psi.shape[0]
+        Ucm = U.transpose(1, 2).contiguous()        # column-major storage
+        pU = (torch.arange(batch, device=psi.device, dtype=torch.int64) * 256 + Ucm.data_ptr())
+        pP = (torch.arange(batch, device=psi.device, dtype=torch.int64) * (psi.stride(0) * 16)
+              + psi.data_ptr())
+        sites = sites.to(device=psi.device, dtype=torch.int32).contiguous()
+        if info is None:
+            info = torch.empty(batch, dtype=torch.int32, device=psi.device)
+        self._sync_stream()
+        st = self._L.bg_zgate2_batched(self._h, int(S), sites.data_ptr(), pU.data_ptr(),
+                                       pP.data_ptr(), batch, info.data_ptr())
+        if st != 0:
+            raise BgemmError("bg_zgate2_batched", st, self.last_invalid_arg())
+        self._keep = (Ucm, pU, pP, sites)
+        return info
 
     def dgemm_vbatched_raw(self, transa, transb, pm, pn, pk, alpha, pA, plda, pB, pldb, beta, pC,
                            pldc, batch, pinfo) -> int:

@@ -14,7 +14,8 @@ LIB = os.path.join(HERE, "libbgemm.so")
 MICRO_LIB = os.path.join(HERE, "libbgemm_microbench.so")
 ARCH = os.environ.get("BG_OFFLOAD_ARCH", "gfx950")
 SOURCES = [os.path.join(CSRC, f) for f in ("bgemm_api.cpp", "bgemm_kernels.hip", "bgemm_lowp.hip",
-                                           "bgemm_complex.hip", "serve.cpp", "serve_kernels.hip")]
+                                           "bgemm_complex.hip", "bgemm_gate.hip", "serve.cpp",
+                                           "serve_kernels.hip")]
 
 # Packed FP32 instructions are kept out of every device build.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

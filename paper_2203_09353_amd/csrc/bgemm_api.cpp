@@ -273,6 +273,25 @@ bg_status_t bg_zgemm_batched(bg_handle_t h, char transa, char transb, int m, int
   return e == hipSuccess ? BG_STATUS_SUCCESS : BG_STATUS_DEVICE_ERROR;
 }
 
+bg_status_t bg_zgate2_batched(bg_handle_t h, int S, const int* d_site, const double* const* dU,
+                              double* const* dPsi, int batch, int* d_info) {
+  if (!valid(h)) return BG_STATUS_INVALID_HANDLE;
+  int bad = 0;
+  if (S < 2 || S > 40) bad = 2;
+  else if (batch > 0 && !d_site) bad = 3;
+  else if (batch > 0 && !dU) bad = 4;
+  else if (batch > 0 && !dPsi) bad = 5;
+  else if (batch < 0) bad = 6;
+  h->last_invalid_arg = bad;
+  if (bad) return BG_STATUS_INVALID_VALUE;
+  if (batch == 0) return BG_STATUS_SUCCESS;
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return BG_STATUS_DEVICE_ERROR;
+  return bg::launch_gate2(S, d_site, dU, dPsi, batch, d_info, h->stream) == hipSuccess
+             ? BG_STATUS_SUCCESS
+             : BG_STATUS_DEVICE_ERROR;
+}
+
 bg_status_t bg_dgemm_vbatched(bg_handle_t h, char transa, char transb, const int* d_m,
                               const int* d_n, const int* d_k, double alpha,
                               const double* const* dA, const int* d_lda, const double* const* dB,

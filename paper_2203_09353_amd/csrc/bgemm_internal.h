@@ -91,6 +91,10 @@ hipError_t launch_zgemm(const ZUniformArgs& a, hipStream_t s);
 hipError_t launch_zscale(const double* beta, double* const* C, int64_t ldc, int m, int n,
                          int batch, hipStream_t s);
 
+// Two-spin gates on batches of 2^S-amplitude states (in place).
+hipError_t launch_gate2(int S, const int* sites, const double* const* U, double* const* psi,
+                        int batch, int* info, hipStream_t s);
+
 // Request loop: one generated factor (column-major n x n at `out`; factor j of
 // `client`, values scaled by `scale`).
 struct FillJob {

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_symbols(header, prefix):
     with open(os.path.join(ROOT, "include", header)) as f:
         text = f.read()
-    return set(re.findall(r"\b(%s_[a-z_]+)\s*\(" % prefix, text))
+    return set(re.findall(r"\b(%s_[a-z0-9_]+)\s*\(" % prefix, text))
 
 
 def test_library_exports_every_declared_symbol():
