@@ -276,6 +276,37 @@ def serving_bench(args, h):
                    "wall_s": round(wall, 3)}
             log(json.dumps(row))
             rows.append(row)
+        # baseline: the same loop serving one request at a time (no batching
+        # across clients), on a 0.1 s slice of the highest offered rate
+        srv.reset()
+        srv.set_max_active(1)
+        a1, c1, l1 = serve.requests(seed, clients, float(args.rates.split(",")[-1]), 0.1)
+        st1, fi1, _ = srv.run(a1, c1, l1)
+        srv.set_max_active(0)
+        n1 = sizes[c1].astype(np.float64)
+        wall1 = float(fi1.max())
+        lat1 = (fi1 - a1) * 1e3
+        serial = {"offered_req_s": float(args.rates.split(",")[-1]), "requests": int(len(a1)),
+                  "achieved_req_s": round(len(a1) / wall1, 1),
+                  "gflops": round(float((2.0 * n1 ** 3 * l1).sum()) / wall1 / 1e9, 1),
+                  "p50_ms": round(float(np.percentile(lat1, 50)), 3),
+                  "p99_ms": round(float(np.percentile(lat1, 99)), 3), "wall_s": round(wall1, 3)}
+        log("one request at a time: " + json.dumps(serial))
+        srv.reset()
+        a, c, l = serve.requests(seed, clients, float(args.rates.split(",")[-1]), args.duration)
+        srv.run(a, c, l)
+        # lock-step annealing sweeps (every client 16 products per sweep, 100
+        # sweeps), launches issued one by one vs replayed from a HIP graph
+        sw = {}
+        for mode in ("eager", "graph"):
+            srv.reset()
+            secs = srv.sweeps(100, 16, graph=(mode == "graph"))
+            fl = float((2.0 * sizes.astype(np.float64) ** 3).sum()) * 16 * 100
+            sw[mode] = {"seconds": round(secs, 4), "gflops": round(fl / secs / 1e9, 1)}
+        sw["graph_speedup"] = round(sw["eager"]["seconds"] / sw["graph"]["seconds"], 3)
+        log("sweeps: " + json.dumps(sw))
+        srv.reset()
+        srv.run(a, c, l)
         # parity: one client of the last run against the CPU replay
         prods = serving.products_per_client(clients, c, l)
         cl = int(np.argmin(np.where(prods > 0, sizes * 1000 + prods, 1 << 40)))
@@ -315,7 +346,9 @@ def serving_bench(args, h):
            "config": {"workload": "config5", "clients": clients,
                       "state_sizes": sorted(set(int(x) for x in sizes)),
                       "duration_s": args.duration},
-           "roofline": roof, "cpu_baseline": cpu, "rates": rows,
+           "roofline": roof, "cpu_baseline": cpu, "rates": rows, "one_at_a_time": serial,
+           "sweeps_100x16": sw,
+           "batching_gain": round(top["achieved_req_s"] / serial["achieved_req_s"], 2),
            "parity_rel_fro_one_client": parity}
     print(json.dumps(out), flush=True)
 

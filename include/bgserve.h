@@ -83,12 +83,34 @@ bg_status_t bs_state(bs_server_t s, int c, double* host_out, long long* products
 bg_status_t bs_fill_factor(unsigned long long seed, int c, long long j, int n, double* out,
                            void* stream);
 
+/* Annealing sweeps in lock step: every client receives `chain` products
+ * per sweep (same factors and states as requests of that length would
+ * give), `sweeps` times.  With use_graph != 0 one sweep (a factor launch and
+ * one batched launch per size per product, then an update of the product
+ * counters on the device) is captured once as a HIP graph -- two when chain
+ * is odd, one per ping-pong parity -- and replayed on the handle's stream
+ * (the capture itself runs on a private stream, since the null stream cannot
+ * be captured); otherwise the same launches are issued one by one.  The results are identical either way.
+ * out_seconds (may be NULL) receives the device time of the sweeps.  The
+ * call allocates and frees its own small arrays and graphs (outside the
+ * timed part); it is synchronous. */
+bg_status_t bs_run_sweeps(bs_server_t s, int sweeps, int chain, int use_graph,
+                          double* out_seconds);
+
+/* Limits the number of requests active at once (0, the default: no limit,
+ * every client with queued work is served at every tick).  With a limit,
+ * the oldest startable requests start first; 1 serves one request at a
+ * time in arrival order (no batching across clients, the baseline that
+ * continuous batching is measured against). */
+bg_status_t bs_set_max_active(bs_server_t s, int max_active);
+
 /* Host-only replay of the scheduler on a virtual clock where every tick
- * lasts tick_s seconds: fills out_start / out_finish as bs_run_schedule
- * would (tick start times), and out_ticks.  Touches no device. */
+ * lasts tick_s seconds, with the given max_active: fills out_start /
+ * out_finish as bs_run_schedule would (tick start and end times), and
+ * out_ticks.  Touches no device. */
 bg_status_t bs_simulate(int num_clients, int n_requests, const double* arrival_s,
-                        const int* client, const int* length, double tick_s, double* out_start,
-                        double* out_finish, long long* out_ticks);
+                        const int* client, const int* length, double tick_s, int max_active,
+                        double* out_start, double* out_finish, long long* out_ticks);
 
 #ifdef __cplusplus
 }

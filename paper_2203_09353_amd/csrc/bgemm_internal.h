@@ -112,6 +112,18 @@ hipError_t launch_fill_factors(const FillJob* d_jobs, int njobs, int max_n,
 // One factor, the same generator (host-side job).
 hipError_t launch_fill_one(double* out, int n, int client, long long j, double scale,
                            unsigned long long seed, hipStream_t s);
+// Annealing sweeps: factor t of a sweep for each job reads the client's
+// product count at the start of the sweep from j0 (device) and uses
+// j = j0[client] + t; k_advance adds `chain` to every j0 entry.
+struct SweepJob {
+  double* out;
+  int n;
+  int client;
+  double scale;
+};
+hipError_t launch_fill_sweep(const SweepJob* d_jobs, int njobs, int max_n, const long long* d_j0,
+                             int t, unsigned long long seed, hipStream_t s);
+hipError_t launch_advance(long long* d_j0, int n, int chain, hipStream_t s);
 // out <- identity (n x n, column-major, ld = n).
 hipError_t launch_identity(double* out, int n, hipStream_t s);
 

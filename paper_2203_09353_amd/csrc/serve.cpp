@@ -39,32 +39,53 @@ struct Scheduler {
     remaining.assign(nc, 0);
     batch.clear();
     next = finished = 0;
+    n_active = 0;
   }
   void admit(double now) {
     while (next < nreq && arrival[next] <= now) queue[client[next]].push_back(next++);
   }
-  // Starts the oldest queued request of every idle client; the tick serves
-  // every client with an active request.  A request whose last product is in
-  // this tick is listed in `last` and leaves its client idle for the next
-  // tick (whose product on the same state is ordered after this one on the
-  // device); it counts as finished when the tick completes.
+  // Starts queued requests of idle clients -- with no limit (max_active 0)
+  // the oldest queued request of every idle client, otherwise the oldest
+  // startable requests while fewer than max_active are active -- then the
+  // tick serves every client with an active request.  A request whose last
+  // product is in this tick is listed in `last` and leaves its client idle
+  // for the next tick (whose product on the same state is ordered after this
+  // one on the device); it counts as finished when the tick completes.
   std::vector<int> last;
+  int max_active = 0;
+  int n_active = 0;
+  void start_request(int c, double now) {
+    const int r = queue[c].front();
+    queue[c].pop_front();
+    active[c] = r;
+    remaining[c] = length[r];
+    start[r] = now;
+    ++n_active;
+  }
   int begin_tick(double now) {
     batch.clear();
     last.clear();
-    for (int c = 0; c < nc; ++c) {
-      if (active[c] < 0 && !queue[c].empty()) {
-        const int r = queue[c].front();
-        queue[c].pop_front();
-        active[c] = r;
-        remaining[c] = length[r];
-        start[r] = now;
+    if (max_active <= 0) {
+      for (int c = 0; c < nc; ++c)
+        if (active[c] < 0 && !queue[c].empty()) start_request(c, now);
+    } else {
+      while (n_active < max_active) {
+        int best = -1;
+        for (int c = 0; c < nc; ++c)
+          if (active[c] < 0 && !queue[c].empty() &&
+              (best < 0 || queue[c].front() < queue[best].front()))
+            best = c;
+        if (best < 0) break;
+        start_request(best, now);
       }
+    }
+    for (int c = 0; c < nc; ++c) {
       if (active[c] >= 0) {
         batch.push_back(c);
         if (--remaining[c] == 0) {
           last.push_back(active[c]);
           active[c] = -1;
+          --n_active;
         }
       }
     }
@@ -111,6 +132,7 @@ struct bs_server {
   const double** h_ptrs[2];       // pinned
   hipEvent_t ev[2];
   hipEvent_t ev0;
+  int max_active;
 };
 
 static const unsigned kServerMagic = 0x5E7BE5E7u;
@@ -245,15 +267,23 @@ bg_status_t bs_fill_factor(unsigned long long seed, int c, long long j, int n, d
              : BG_STATUS_DEVICE_ERROR;
 }
 
+bg_status_t bs_set_max_active(bs_server_t s, int max_active) {
+  if (!valid(s)) return BG_STATUS_INVALID_HANDLE;
+  if (max_active < 0) return BG_STATUS_INVALID_VALUE;
+  s->max_active = max_active;
+  return BG_STATUS_SUCCESS;
+}
+
 bg_status_t bs_simulate(int num_clients, int n_requests, const double* arrival_s,
-                        const int* client, const int* length, double tick_s, double* out_start,
-                        double* out_finish, long long* out_ticks) {
-  if (num_clients <= 0 || !(tick_s > 0.0) ||
+                        const int* client, const int* length, double tick_s, int max_active,
+                        double* out_start, double* out_finish, long long* out_ticks) {
+  if (num_clients <= 0 || !(tick_s > 0.0) || max_active < 0 ||
       !bs::valid_schedule(num_clients, n_requests, arrival_s, client, length) ||
       (n_requests > 0 && (!out_start || !out_finish)))
     return BG_STATUS_INVALID_VALUE;
   bs::Scheduler sc;
   sc.init(num_clients, n_requests, arrival_s, client, length, out_start, out_finish);
+  sc.max_active = max_active;
   double now = 0.0;
   long long ticks = 0;
   while (!sc.done()) {
@@ -282,6 +312,7 @@ bg_status_t bs_run_schedule(bs_server_t s, int n_requests, const double* arrival
   const hipStream_t stream = (hipStream_t)sv;
   bs::Scheduler sc;
   sc.init(s->nc, n_requests, arrival_s, client, length, out_start, out_finish);
+  sc.max_active = s->max_active;
   using clk = std::chrono::steady_clock;
   // Up to two ticks in flight: the host prepares and launches tick t + 1
   // while tick t runs.  A tick's completion time is read from its event
@@ -372,6 +403,147 @@ bg_status_t bs_run_schedule(bs_server_t s, int n_requests, const double* arrival
   }
   if (out_ticks) *out_ticks = ticks;
   return BG_STATUS_SUCCESS;
+}
+
+bg_status_t bs_run_sweeps(bs_server_t s, int sweeps, int chain, int use_graph,
+                          double* out_seconds) {
+  if (!valid(s)) return BG_STATUS_INVALID_HANDLE;
+  if (sweeps < 0 || chain < 1) return BG_STATUS_INVALID_VALUE;
+  void* sv = nullptr;
+  bg_get_stream(s->h, &sv);
+  const hipStream_t stream = (hipStream_t)sv;
+  const int nc = s->nc;
+  // clients grouped by size; per tick t and starting parity p the pointer
+  // triples (factor, state in, state out)
+  std::vector<int> order(nc);
+  for (int c = 0; c < nc; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return s->sizes[a] < s->sizes[b]; });
+  int max_n = 0;
+  std::vector<bg::SweepJob> jobs(nc);
+  std::vector<long long> j0(nc);
+  for (int i = 0; i < nc; ++i) {
+    const int c = order[i];
+    jobs[i] = bg::SweepJob{s->fac[c], s->sizes[c], c, s->scale[c]};
+    max_n = std::max(max_n, s->sizes[c]);
+  }
+  for (int c = 0; c < nc; ++c) j0[c] = s->products[c];
+  std::vector<const double*> ptrs((size_t)2 * chain * 3 * nc);
+  for (int p = 0; p < 2; ++p)
+    for (int t = 0; t < chain; ++t) {
+      const double** row = ptrs.data() + ((size_t)p * chain + t) * 3 * nc;
+      for (int i = 0; i < nc; ++i) {
+        const int c = order[i];
+        const int cur = s->cur[c] ^ p ^ (t & 1);
+        row[i] = s->fac[c];
+        row[nc + i] = s->st[cur][c];
+        row[2 * nc + i] = s->st[cur ^ 1][c];
+      }
+    }
+  bg::SweepJob* d_jobs = nullptr;
+  long long* d_j0 = nullptr;
+  const double** d_ptrs = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bg_status_t st = BG_STATUS_SUCCESS;
+  auto fail = [&](bg_status_t x) { if (st == BG_STATUS_SUCCESS) st = x; };
+  if (hipMalloc(&d_jobs, nc * sizeof(bg::SweepJob)) != hipSuccess ||
+      hipMalloc(&d_j0, nc * sizeof(long long)) != hipSuccess ||
+      hipMalloc((void**)&d_ptrs, ptrs.size() * sizeof(double*)) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    fail(BG_STATUS_ALLOC_FAILED);
+  if (st == BG_STATUS_SUCCESS &&
+      (hipMemcpy(d_jobs, jobs.data(), nc * sizeof(bg::SweepJob), hipMemcpyHostToDevice) !=
+           hipSuccess ||
+       hipMemcpy(d_j0, j0.data(), nc * sizeof(long long), hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy((void*)d_ptrs, ptrs.data(), ptrs.size() * sizeof(double*),
+                 hipMemcpyHostToDevice) != hipSuccess))
+    fail(BG_STATUS_DEVICE_ERROR);
+  // one sweep starting at parity p: per tick the factors, then one batched
+  // launch per size; finally the product counters advance
+  auto enqueue_sweep = [&](int p, hipStream_t q) -> bg_status_t {
+    for (int t = 0; t < chain; ++t) {
+      const double** row = d_ptrs + ((size_t)p * chain + t) * 3 * nc;
+      if (bg::launch_fill_sweep(d_jobs, nc, max_n, d_j0, t, s->seed, q) != hipSuccess)
+        return BG_STATUS_DEVICE_ERROR;
+      for (int g0 = 0; g0 < nc;) {
+        int g1 = g0;
+        const int n = s->sizes[order[g0]];
+        while (g1 < nc && s->sizes[order[g1]] == n) ++g1;
+        const bg_status_t r = bg_dgemm_batched(s->h, 'N', 'N', n, n, n, 1.0, row + g0, n,
+                                               row + nc + g0, n, 0.0,
+                                               (double* const*)(row + 2 * nc + g0), n, g1 - g0);
+        if (r != BG_STATUS_SUCCESS) return r;
+        g0 = g1;
+      }
+    }
+    return bg::launch_advance(d_j0, nc, chain, q) == hipSuccess ? BG_STATUS_SUCCESS
+                                                                 : BG_STATUS_DEVICE_ERROR;
+  };
+  const int nparity = (chain & 1) ? 2 : 1;
+  if (st == BG_STATUS_SUCCESS && use_graph) {
+    // The handle's stream may be the null stream, which cannot be captured:
+    // capture on a private stream (default priority) with the handle
+    // pointed at it, then replay on the handle's stream.
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+      fail(BG_STATUS_DEVICE_ERROR);
+    } else {
+      bg_set_stream(s->h, (void*)cap);
+      for (int p = 0; p < nparity && st == BG_STATUS_SUCCESS; ++p) {
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+          fail(BG_STATUS_DEVICE_ERROR);
+          break;
+        }
+        const bg_status_t r = enqueue_sweep(p, cap);
+        const hipError_t ec = hipStreamEndCapture(cap, &graph[p]);
+        if (r != BG_STATUS_SUCCESS) fail(r);
+        else if (ec != hipSuccess ||
+                 hipGraphInstantiate(&exec[p], graph[p], nullptr, nullptr, 0) != hipSuccess)
+          fail(BG_STATUS_DEVICE_ERROR);
+      }
+      bg_set_stream(s->h, sv);
+      (void)hipStreamDestroy(cap);
+    }
+  }
+  if (st == BG_STATUS_SUCCESS) {
+    if (hipStreamSynchronize(stream) != hipSuccess || hipEventRecord(e0, stream) != hipSuccess)
+      fail(BG_STATUS_DEVICE_ERROR);
+    for (int w = 0; w < sweeps && st == BG_STATUS_SUCCESS; ++w) {
+      const int p = (chain & 1) ? (w & 1) : 0;
+      if (use_graph) {
+        if (hipGraphLaunch(exec[p], stream) != hipSuccess) fail(BG_STATUS_DEVICE_ERROR);
+      } else {
+        const bg_status_t r = enqueue_sweep(p, stream);
+        if (r != BG_STATUS_SUCCESS) fail(r);
+      }
+    }
+    if (st == BG_STATUS_SUCCESS &&
+        (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+      fail(BG_STATUS_DEVICE_ERROR);
+    float ms = 0.f;
+    if (st == BG_STATUS_SUCCESS && out_seconds && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      *out_seconds = (double)ms * 1e-3;
+  }
+  if (st == BG_STATUS_SUCCESS) {
+    const long long done = (long long)sweeps * chain;
+    for (int c = 0; c < nc; ++c) {
+      s->products[c] += done;
+      s->cur[c] ^= (int)(done & 1);
+    }
+  }
+  (void)hipStreamSynchronize(stream);
+  for (int p = 0; p < 2; ++p) {
+    if (exec[p]) (void)hipGraphExecDestroy(exec[p]);
+    if (graph[p]) (void)hipGraphDestroy(graph[p]);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (d_jobs) (void)hipFree(d_jobs);
+  if (d_j0) (void)hipFree(d_j0);
+  if (d_ptrs) (void)hipFree((void*)d_ptrs);
+  return st;
 }
 
 }  // extern "C"

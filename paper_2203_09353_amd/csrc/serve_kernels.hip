@@ -57,6 +57,18 @@ __global__ __launch_bounds__(256) void k_fill_factors(const FillJob* __restrict_
   fill_job(jb, seed, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
 }
 
+__global__ __launch_bounds__(256) void k_fill_sweep(const SweepJob* __restrict__ jobs,
+                                                    const long long* __restrict__ j0, int t,
+                                                    uint64_t seed) {
+  const SweepJob sj = jobs[blockIdx.y];
+  const FillJob jb{sj.out, j0[sj.client] + t, sj.n, sj.client, sj.scale};
+  fill_job(jb, seed, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+}
+
+__global__ __launch_bounds__(256) void k_advance(long long* __restrict__ j0, int n, int chain) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) j0[i] += chain;
+}
+
 __global__ __launch_bounds__(256) void k_fill_one(FillJob jb, uint64_t seed) {
   fill_job(jb, seed, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
 }
@@ -80,6 +92,21 @@ hipError_t launch_fill_factors(const FillJob* d_jobs, int njobs, int max_n,
   const int64_t blocks = ((int64_t)max_n * max_n + 3) / 4;
   hipLaunchKernelGGL(k_fill_factors, dim3(grid_for(blocks), njobs), dim3(256), 0, s, d_jobs,
                      (uint64_t)seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_sweep(const SweepJob* d_jobs, int njobs, int max_n, const long long* d_j0,
+                             int t, unsigned long long seed, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  if (njobs > 65535 || max_n < 1) return hipErrorInvalidValue;
+  const int64_t blocks = ((int64_t)max_n * max_n + 3) / 4;
+  hipLaunchKernelGGL(k_fill_sweep, dim3(grid_for(blocks), njobs), dim3(256), 0, s, d_jobs, d_j0, t,
+                     (uint64_t)seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(long long* d_j0, int n, int chain, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(grid_for(n)), dim3(256), 0, s, d_j0, n, chain);
   return hipGetLastError();
 }
 

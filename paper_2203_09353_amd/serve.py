@@ -43,7 +43,11 @@ def _lib():
         L.bs_fill_factor.restype = i
         L.bs_fill_factor.argtypes = [u64, i, ll, i, vp, vp]
         L.bs_simulate.restype = i
-        L.bs_simulate.argtypes = [i, i, vp, vp, vp, d, vp, vp, ctypes.POINTER(ll)]
+        L.bs_simulate.argtypes = [i, i, vp, vp, vp, d, i, vp, vp, ctypes.POINTER(ll)]
+        L.bs_run_sweeps.restype = i
+        L.bs_run_sweeps.argtypes = [vp, i, i, i, ctypes.POINTER(d)]
+        L.bs_set_max_active.restype = i
+        L.bs_set_max_active.argtypes = [vp, i]
         _set = True
     return L
 
@@ -61,15 +65,15 @@ def bytes_needed(sizes) -> int:
     return int(_lib().bs_bytes_needed(len(s), _ptr(s)))
 
 
-def simulate(num_clients, arrivals, clients, lengths, tick_s):
+def simulate(num_clients, arrivals, clients, lengths, tick_s, max_active=0):
     """Host-only replay of the scheduler on a virtual clock (no device):
     returns (start, finish, ticks)."""
     a, c, l = _arr(arrivals, np.float64), _arr(clients, np.int32), _arr(lengths, np.int32)
     n = len(a)
     st, fi = np.zeros(n), np.zeros(n)
     ticks = ctypes.c_longlong()
-    r = _lib().bs_simulate(num_clients, n, _ptr(a), _ptr(c), _ptr(l), float(tick_s), _ptr(st),
-                           _ptr(fi), ctypes.byref(ticks))
+    r = _lib().bs_simulate(num_clients, n, _ptr(a), _ptr(c), _ptr(l), float(tick_s),
+                           int(max_active), _ptr(st), _ptr(fi), ctypes.byref(ticks))
     if r != 0:
         raise bgemm.BgemmError("bs_simulate", r)
     return st, fi, ticks.value
@@ -109,6 +113,22 @@ class Server:
             self.close()
         except Exception:
             pass
+
+    def sweeps(self, sweeps: int, chain: int, graph: bool):
+        """Lock-step annealing sweeps; returns the device seconds."""
+        self.handle._sync_stream()
+        secs = ctypes.c_double()
+        r = self.L.bs_run_sweeps(self._s, int(sweeps), int(chain), 1 if graph else 0,
+                                 ctypes.byref(secs))
+        if r != 0:
+            raise bgemm.BgemmError("bs_run_sweeps", r)
+        return secs.value
+
+    def set_max_active(self, k: int):
+        """0: continuous batching (default); 1: one request at a time."""
+        r = self.L.bs_set_max_active(self._s, int(k))
+        if r != 0:
+            raise bgemm.BgemmError("bs_set_max_active", r)
 
     def reset(self):
         self.handle._sync_stream()

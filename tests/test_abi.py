@@ -31,7 +31,8 @@ def test_library_exports_the_request_loop():
     L = serve._lib()
     declared = _declared_symbols("bgserve.h", "bs")
     assert declared == {"bs_create", "bs_destroy", "bs_bytes_needed", "bs_reset",
-                        "bs_run_schedule", "bs_state", "bs_fill_factor", "bs_simulate"}
+                        "bs_run_schedule", "bs_state", "bs_fill_factor", "bs_simulate",
+                        "bs_set_max_active", "bs_run_sweeps"}
     for name in declared:
         assert hasattr(L, name), name
     # host-side argument checks need no device

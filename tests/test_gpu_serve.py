@@ -93,3 +93,52 @@ def test_budget_and_argument_errors(h):
         assert ticks == 0
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("chain", [2, 3])
+def test_graph_sweeps_equal_eager_sweeps(h, chain):
+    """Lock-step sweeps replayed from a captured graph give the same bits as
+    the same launches issued one by one, for 1, 2 and 3 replays (each count
+    checked, with unrelated eager work and synchronisation in between), and
+    match the CPU replay."""
+    srv = serve.Server(h, SIZES, seed=17)
+    A = torch.rand(4, 40, 40, dtype=torch.float64, device="cuda")
+    Cx = torch.zeros_like(A)
+    try:
+        for sweeps in (1, 2, 3):
+            srv.reset()
+            t_eager = srv.sweeps(sweeps, chain, graph=False)
+            eager = {cl: srv.state(cl) for cl in range(len(SIZES))}
+            h.batched(A, A, Cx, 40, 40, 40, 1.0, 0.0)        # unrelated eager work
+            torch.cuda.synchronize()
+            srv.reset()
+            t_graph = srv.sweeps(sweeps, chain, graph=True)
+            h.batched(A, A, Cx, 40, 40, 40, 1.0, 0.0)
+            torch.cuda.synchronize()
+            assert t_eager > 0 and t_graph > 0
+            for cl, n in enumerate(SIZES):
+                S, p = srv.state(cl)
+                E, pe = eager[cl]
+                assert p == pe == sweeps * chain
+                assert np.array_equal(S.view(np.int64), E.view(np.int64)), (sweeps, chain, cl)
+        for cl, n in enumerate(SIZES[:3]):
+            ref = serving.final_state(17, cl, n, 3 * chain)
+            S, _ = srv.state(cl)
+            assert np.linalg.norm(S - ref) <= 1e-13 * 3 * chain * np.linalg.norm(ref)
+    finally:
+        srv.close()
+
+
+def test_sweeps_then_requests_continue_the_same_chain(h):
+    # sweeps and requests share the product counter: 2 sweeps of 2, then a
+    # request of 3 for client 1, equal the replay of 7 products
+    srv = serve.Server(h, SIZES, seed=23)
+    try:
+        srv.sweeps(2, 2, graph=True)
+        srv.run([0.0], [1], [3])
+        S, p = srv.state(1)
+        assert p == 7
+        ref = serving.final_state(23, 1, SIZES[1], 7)
+        assert np.linalg.norm(S - ref) <= 1e-12 * np.linalg.norm(ref)
+    finally:
+        srv.close()

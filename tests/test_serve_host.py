@@ -102,3 +102,32 @@ def test_replay_pins():
     ref = F1 @ F0
     assert np.linalg.norm(S2 - ref) <= 1e-14 * np.linalg.norm(ref)
     assert list(serving.products_per_client(3, [0, 2, 0], [4, 1, 2])) == [6, 0, 1]
+
+
+def test_serial_baseline_runs_one_request_at_a_time():
+    nc = 8
+    a, c, l = serve.requests(4, nc, 3000.0, 0.05)
+    tick = 1e-4
+    st, fi, ticks = serve.simulate(nc, a, c, l, tick, max_active=1)
+    order = np.argsort(st, kind="stable")
+    assert np.array_equal(order, np.arange(len(a)))        # started in arrival order
+    assert ticks == l.sum()                                 # one product per tick
+    assert np.all(st[1:] >= fi[:-1] - 1e-12)                # never two at once
+    prev = 0.0
+    for r in range(len(a)):                                 # work conserving
+        assert st[r] - max(a[r], prev) <= tick + 1e-12
+        prev = fi[r]
+    # with no limit the same schedule needs fewer ticks and finishes sooner
+    st2, fi2, ticks2 = serve.simulate(nc, a, c, l, tick)
+    assert ticks2 < ticks and fi2.max() < fi.max()
+
+
+def test_limited_active_requests():
+    nc = 8
+    a, c, l = serve.requests(6, nc, 20000.0, 0.02)
+    st, fi, ticks = serve.simulate(nc, a, c, l, 1e-4, max_active=3)
+    # at every tick start at most three requests are in flight
+    for t in np.unique(st):
+        assert np.sum((st <= t) & (fi > t)) <= 3
+    with pytest.raises(bgemm.BgemmError):
+        serve.simulate(nc, a, c, l, 1e-4, max_active=-1)
