@@ -42,6 +42,29 @@ Modes
   Since every rounding is fixed in kind and order, a device implementing
   these steps must match this oracle bit for bit.
 
+``i8emu<s>`` emulated binary64 with s int8 digit slices (s = 1..8), after
+           Ozaki, Ogita, Oishi and Rump (Numer. Algorithms 59, 2012) with
+           whole-row scaling and integer digit products, so that each
+           diagonal is one exact integer sum over all of k:
+    1. For row i of A, e_i is the exponent with max_p |A[i,p]| in
+       [2^(e-1), 2^e) over all of k (frexp; 0 for an all-zero row); likewise
+       f_j for column j of B.
+    2. X[i,p] = rint(A[i,p] 2^(8s-2-e_i)) (ties to even), an integer with
+       |X| <= 2^(8s-2); Y[p,j] likewise with f_j.
+    3. Signed base-256 digits: X = sum_{t=1..s} d_t 256^(s-t) with
+       d_t in [-128, 127] for t >= 2, taken from the least significant end
+       (d_t = ((X + 128) mod 256) - 128, then X <- (X - d_t) / 256); what
+       remains is d_1, in [-64, 64].  Every digit is an int8.
+    4. For g = 2 .. s+1, S_g[i,j] = sum over t + u = g of
+       sum_p dA_t[i,p] dB_u[p,j]: an exact integer (pairs with t + u > s + 1
+       are dropped: s (s + 1) / 2 slice products).
+    5. In binary64: T = S_{s+1}; for g = s down to 2: T = S_g + T 2^-8
+       (rounded add; the scaled term is exact); V = T 2^(e_i + f_j - 12).
+    6. C = alpha V + beta C (the binary64 rules).
+  Truncation and dropped pairs bound the error by
+  1.02 s k 2^(2-8s) 2^(e_i+f_j) per entry, the roundings of step 5 by about
+  s u k 2^(e_i+f_j) (u = 2^-53).
+
 Error reference
 ---------------
 ``dot2_gemm`` is the compensated product of Ogita, Rump and Oishi ("Accurate
@@ -128,6 +151,56 @@ def emulated_gemm(A, B, s, alpha=1.0, beta=0.0, C0=None):
     if beta == 0.0:
         return alpha * acc
     return alpha * acc + beta * np.asarray(C0, dtype=np.float64)
+
+
+def row_exponents(A):
+    """e[i]: frexp exponent of max_p |A[i, p]| over the whole row (0 for an
+    all-zero row)."""
+    A = np.asarray(A, dtype=np.float64)
+    mx = np.max(np.abs(A), axis=1) if A.shape[1] else np.zeros(A.shape[0])
+    _, e = np.frexp(mx)
+    return np.where(mx > 0, e, 0).astype(np.int64)
+
+
+def int8_digits(X, s):
+    """Signed base-256 digits d_1..d_s (int64 arrays, d_1 most significant)
+    of the integers X, |X| <= 2^(8s-2), step 3 of the i8emu mode."""
+    X = np.asarray(X, dtype=np.int64).copy()
+    low = []
+    for _ in range(s - 1):
+        d = np.mod(X + 128, 256) - 128
+        low.append(d)
+        X = (X - d) // 256
+    return [X] + low[::-1]
+
+
+def int8_emulated_gemm(A, B, s, alpha=1.0, beta=0.0, C0=None):
+    """The i8emu<s> mode, steps 1-6 above.  A (m, k), B (k, n) float64."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    m, k = A.shape
+    n = B.shape[1]
+    e = row_exponents(A)
+    f = row_exponents(B.T)
+    X = np.rint(np.ldexp(A, (8 * s - 2) - e[:, None])).astype(np.int64)
+    Y = np.rint(np.ldexp(B, (8 * s - 2) - f[None, :])).astype(np.int64)
+    da = int8_digits(X, s)
+    db = int8_digits(Y, s)
+    S = {}
+    for g in range(2, s + 2):
+        acc = np.zeros((m, n), dtype=np.int64)
+        for t in range(1, g):
+            u = g - t
+            if t <= s and u <= s:
+                acc += da[t - 1] @ db[u - 1]                 # exact int64
+        S[g] = acc
+    T = S[s + 1].astype(np.float64)
+    for g in range(s, 1, -1):
+        T = S[g].astype(np.float64) + T * 2.0 ** -8
+    V = np.ldexp(T, e[:, None] + f[None, :] - 12)
+    if beta == 0.0:
+        return alpha * V
+    return alpha * V + beta * np.asarray(C0, dtype=np.float64)
 
 
 def _two_sum(a, b):
