@@ -1,7 +1,7 @@
 """Benchmark of the batched FP64 GEMM hot path on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload config2+vb]
-    python bench.py --workload config4 [--modes fp64,fp32,bf16,emu3,emu6,emu7]
+    python bench.py --workload config4 [--modes fp64,fp32,bf16,emu3,emu6,emu7,i8emu6,i8emu7,i8emu8]
     python bench.py --workload config5 [--rates 1000,5000,20000,50000] [--duration 2]
     python bench.py --workload gram15 [--steps K]
     python bench.py --workload gate21 [--steps K]
@@ -45,6 +45,7 @@ PEAK_FP64 = 78.6e12      # MI355X published FP64 (vector and matrix), flop/s
 PEAK_HBM = 8.0e12        # MI355X published HBM3E bandwidth, bytes/s
 PEAK_FP32_MFMA = 157.3e12  # dense binary32 matrix cores
 PEAK_BF16_MFMA = 2.5e15    # dense bfloat16 matrix cores
+PEAK_INT8_MFMA = 5.0e15    # dense int8 matrix cores (operations per second)
 FP64_ACCURACY = 1e-13      # relative Frobenius error that counts as binary64 accuracy
 METRIC = "batched GEMM GFLOP/s at FP64 accuracy, % roofline; p50/p99 request latency"
 
@@ -89,12 +90,15 @@ def part_launch(h, p):
 
 
 def parse_mode(name: str):
-    """'fp64' | 'fp32' | 'bf16' | 'emu<s>' -> (bg_mode_t value, slices)."""
+    """'fp64' | 'fp32' | 'bf16' | 'emu<s>' | 'i8emu<s>' -> (bg_mode_t value,
+    slices)."""
     fixed = {"fp64": (0, 0), "fp32": (1, 0), "bf16": (2, 0)}
     if name in fixed:
         return fixed[name]
     if name.startswith("emu") and name[3:].isdigit() and 1 <= int(name[3:]) <= 8:
         return (3, int(name[3:]))
+    if name.startswith("i8emu") and name[5:].isdigit() and 1 <= int(name[5:]) <= 8:
+        return (4, int(name[5:]))
     raise ValueError("unknown precision mode " + name)
 
 
@@ -112,11 +116,12 @@ def mode_flops(p, mode):
     """(binary64-equivalent flops, flops the matrix cores execute) per launch."""
     f = p.flops
     code, s = mode
-    return f, (f * s * (s + 1) / 2 if code == 3 else f)
+    return f, (f * s * (s + 1) / 2 if code in (3, 4) else f)
 
 
 def mode_peak(mode):
-    return {0: PEAK_FP64, 1: PEAK_FP32_MFMA, 2: PEAK_BF16_MFMA, 3: PEAK_BF16_MFMA}[mode[0]]
+    return {0: PEAK_FP64, 1: PEAK_FP32_MFMA, 2: PEAK_BF16_MFMA, 3: PEAK_BF16_MFMA,
+            4: PEAK_INT8_MFMA}[mode[0]]
 
 
 def precision_bench(args, h, parts):
@@ -153,8 +158,9 @@ def precision_bench(args, h, parts):
             fro.append(P.relative_errors(G, d2)[0])
             fro64.append(P.relative_errors(G, f64)[0])
             comp.append(float(np.max(np.abs(G - d2) / np.where(mag > 0, mag, 1.0))))
-            if mode[0] == 3 and j == 0:
-                ref = P.emulated_gemm(Am, Bm, mode[1])
+            if mode[0] in (3, 4) and j == 0:
+                emu = P.emulated_gemm if mode[0] == 3 else P.int8_emulated_gemm
+                ref = emu(Am, Bm, mode[1])
                 exact = bool(np.array_equal(G.view(np.int64), ref.view(np.int64)))
         for _ in range(args.warmup):
             mode_launch(h, p, mode)
@@ -197,7 +203,8 @@ def precision_bench(args, h, parts):
     if not args.no_cpu:
         log("timing the CPU oracle of mode %s on a sample" % best["mode"])
         cpu = precision_cpu_baseline(p, bmode, args.cpu_seconds)
-    dtype = {0: "f64", 1: "f32", 2: "bf16", 3: "bf16 slices (f32 sums, f64 recombination)"}[bmode[0]]
+    dtype = {0: "f64", 1: "f32", 2: "bf16", 3: "bf16 slices (f32 sums, f64 recombination)",
+             4: "int8 slices (int32 sums, f64 recombination)"}[bmode[0]]
     out = {"metric": METRIC, "value": best["gflops_fp64_equiv"], "unit": "GFLOP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
@@ -206,6 +213,8 @@ def precision_bench(args, h, parts):
                       "mode": best["mode"],
                       "accuracy_rule": "max rel Frobenius vs Dot2 <= %g" % FP64_ACCURACY},
            "roofline": roof, "cpu_baseline": cpu, "modes": rows,
+           "gain_vs_fp64": next((round(best["gflops_fp64_equiv"] / r["gflops_fp64_equiv"], 3)
+                                 for r in rows if r["mode"] == "fp64"), None),
            "fp64_oracle_floor_vs_dot2": float("%.3e" % oracle_floor)}
     print(json.dumps(out), flush=True)
 
@@ -233,6 +242,8 @@ def precision_cpu_baseline(p, mode, seconds):
             t0 = time.perf_counter()
             if mode[0] == 3:
                 P.emulated_gemm(Am, Bm, mode[1])
+            elif mode[0] == 4:
+                P.int8_emulated_gemm(Am, Bm, mode[1])
             else:
                 P.reference_product(Am, Bm, "fp32" if mode[0] == 1 else "bf16")
                 used = threads
@@ -601,7 +612,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=3, help="sampled parity instances per part")
-    ap.add_argument("--modes", default="fp64,fp32,bf16,emu3,emu6,emu7",
+    ap.add_argument("--modes", default="fp64,fp32,bf16,emu3,emu6,emu7,i8emu6,i8emu7,i8emu8",
                     help="precision modes timed by --workload config4")
     ap.add_argument("--rates", default="1000,5000,20000,50000",
                     help="offered request rates (per second) for --workload config5")

@@ -143,13 +143,30 @@ bg_status_t bg_dgemm_vbatched(bg_handle_t h, char transa, char transb,
  *                 reproducible bit for bit.  The error falls by about 2^-8 per
  *                 added slice; 7 slices reach the binary64 path's accuracy on
  *                 well-scaled data.
+ *   BG_MODE_EMU_I8 binary64 emulated with `slices` (1..8) int8 digit slices
+ *                 per operand (Ozaki et al., Numer. Algorithms 59, 2012): each
+ *                 row of A and column of B is scaled over all of k by a power
+ *                 of two, rounded to an integer of 8 * slices - 1 bits and
+ *                 cut into signed base-256 digits; the digit products up to
+ *                 the (slices + 1)-th diagonal are summed exactly in int32 on
+ *                 the int8 matrix cores and recombined in binary64 in a fixed
+ *                 order (bit-reproducible).  Needs k <= 8192 (else
+ *                 NOT_SUPPORTED) and (m + n) * 4 bytes of the handle's
+ *                 workspace per instance for at least one instance (else
+ *                 ALLOC_FAILED); larger batches run in groups that fit.
+ *                 Finite inputs only.  The error is bounded by about
+ *                 slices * k * 2^(2 - 8 slices) * 2^(e_i + f_j) per entry (e_i,
+ *                 f_j the exponents of row i's and column j's largest
+ *                 magnitudes); 7 slices stay within 1e-14 relative on data
+ *                 spread over 2^+-20, 8 match the binary64 path.
  * The paper computes in binary64 only (Section II); these modes are an
  * extension for callers that trade accuracy for matrix-core throughput. */
 typedef enum {
   BG_MODE_FP64 = 0,
   BG_MODE_FP32 = 1,
   BG_MODE_BF16 = 2,
-  BG_MODE_EMU = 3
+  BG_MODE_EMU = 3,
+  BG_MODE_EMU_I8 = 4
 } bg_mode_t;
 
 /* Uniform batch as bg_dgemm_batched, computed in `mode`.  Arguments, layout,
@@ -158,7 +175,8 @@ typedef enum {
  * every mode).  The reduced modes take non-transposed operands only
  * (transa == transb == 'N'); a transposed operand with such a mode returns
  * BG_STATUS_NOT_SUPPORTED.  A bad mode records argument number 101, a slice
- * count outside 1..8 for BG_MODE_EMU records 102 (both INVALID_VALUE). */
+ * count outside 1..8 for BG_MODE_EMU or BG_MODE_EMU_I8 records 102 (both
+ * INVALID_VALUE). */
 bg_status_t bg_gemm_batched_mode(bg_handle_t h, int mode, int slices, char transa, char transb,
                                  int m, int n, int k, double alpha,
                                  const double* const* dA, int lda,

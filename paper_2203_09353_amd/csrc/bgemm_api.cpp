@@ -205,8 +205,11 @@ bg_status_t bg_gemm_batched_mode(bg_handle_t h, int mode, int slices, char trans
     return bg_dgemm_batched(h, transa, transb, m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc,
                             batch);
   int bad = 0;
-  if (mode != BG_MODE_FP32 && mode != BG_MODE_BF16 && mode != BG_MODE_EMU) bad = 101;
-  else if (mode == BG_MODE_EMU && (slices < 1 || slices > 8)) bad = 102;
+  if (mode != BG_MODE_FP32 && mode != BG_MODE_BF16 && mode != BG_MODE_EMU &&
+      mode != BG_MODE_EMU_I8)
+    bad = 101;
+  else if ((mode == BG_MODE_EMU || mode == BG_MODE_EMU_I8) && (slices < 1 || slices > 8))
+    bad = 102;
   else bad = bg_check_batched_args(transa, transb, m, n, k, dA, lda, dB, ldb, dC, ldc, batch);
   h->last_invalid_arg = bad;
   if (bad) return BG_STATUS_INVALID_VALUE;
@@ -227,7 +230,15 @@ bg_status_t bg_gemm_batched_mode(bg_handle_t h, int mode, int slices, char trans
     a.alpha = alpha; a.beta = beta;
     a.A = dA; a.lda = lda; a.B = dB; a.ldb = ldb; a.C = dC; a.ldc = ldc;
     a.batch = batch;
-    e = bg::launch_uniform_lowp(a, mode, slices, h->stream);
+    if (mode == BG_MODE_EMU_I8) {
+      // exact int32 diagonal sums need k <= 8192; the exponents of at least
+      // one instance must fit the workspace
+      if (k > 8192) return BG_STATUS_NOT_SUPPORTED;
+      if (h->ws_bytes < (size_t)(m + n) * sizeof(int)) return BG_STATUS_ALLOC_FAILED;
+      e = bg::launch_emu8(a, slices, h->ws, h->ws_bytes, h->stream);
+    } else {
+      e = bg::launch_uniform_lowp(a, mode, slices, h->stream);
+    }
     if (e == hipErrorInvalidValue) return BG_STATUS_NOT_SUPPORTED;
   }
   return e == hipSuccess ? BG_STATUS_SUCCESS : BG_STATUS_DEVICE_ERROR;

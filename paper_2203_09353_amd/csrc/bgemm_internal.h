@@ -42,6 +42,11 @@ hipError_t launch_uniform(const UniformArgs& a, TileClass cls, hipStream_t s);
 // mode 1 binary32, 2 bfloat16, 3 emulated binary64 with `slices` (1..8)
 // bfloat16 digit slices.  hipErrorInvalidValue for grids beyond int32.
 hipError_t launch_uniform_lowp(const UniformArgs& a, int mode, int slices, hipStream_t s);
+// Emulated binary64 on int8 digit slices (NN, k <= 8192): per group of
+// instances, row / column exponents into the workspace (m + n ints per
+// instance), then the product.  hipErrorInvalidValue when the workspace holds
+// no instance or slices is outside 1..8.
+hipError_t launch_emu8(const UniformArgs& a, int slices, void* ws, size_t ws_bytes, hipStream_t s);
 
 // Launches C_i <- beta * C_i (beta != 1) for every instance, used when the
 // product term vanishes (alpha == 0 or k == 0).

@@ -51,6 +51,26 @@ __global__ void k_mfma_bf16_once(const unsigned short* a, const unsigned short* 
   for (int v = 0; v < 4; ++v) d[4 * l + v] = acc[v];
 }
 
+// One v_mfma_i32_16x16x64_i8: a/b[16*64] per-lane int8 values (element e of
+// lane l at 16*l + e, byte e of the lane's 16-byte operand), c/d[4*64] int32.
+typedef int i4 __attribute__((ext_vector_type(4)));
+__global__ void k_mfma_i8_once(const signed char* a, const signed char* b, const int* c, int* d) {
+  const int l = threadIdx.x;
+  i4 va, vb;
+  for (int w = 0; w < 4; ++w) {
+    unsigned ua = 0, ub = 0;
+    for (int e = 0; e < 4; ++e) {
+      ua |= (unsigned)(unsigned char)a[16 * l + 4 * w + e] << (8 * e);
+      ub |= (unsigned)(unsigned char)b[16 * l + 4 * w + e] << (8 * e);
+    }
+    va[w] = (int)ua;
+    vb[w] = (int)ub;
+  }
+  i4 acc = {c[4 * l], c[4 * l + 1], c[4 * l + 2], c[4 * l + 3]};
+  acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(va, vb, acc, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) d[4 * l + v] = acc[v];
+}
+
 // CHAINS independent accumulators per wave, `iters` rounds of CHAINS MFMAs.
 template <int CHAINS>
 __global__ __launch_bounds__(256) void k_mfma_peak(double* sink, int iters, double seed) {
@@ -235,6 +255,11 @@ int mb_mfma_f32_16x16x4(const float* a, const float* b, const float* c, float* d
 int mb_mfma_bf16_16x16x32(const unsigned short* a, const unsigned short* b, const float* c,
                           float* d) {
   hipLaunchKernelGGL(k_mfma_bf16_once, dim3(1), dim3(64), 0, 0, a, b, c, d);
+  return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
+}
+
+int mb_mfma_i8_16x16x64(const signed char* a, const signed char* b, const int* c, int* d) {
+  hipLaunchKernelGGL(k_mfma_i8_once, dim3(1), dim3(64), 0, 0, a, b, c, d);
   return hipDeviceSynchronize() == hipSuccess ? 0 : 1;
 }
 

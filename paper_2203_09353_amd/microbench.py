@@ -29,6 +29,8 @@ def lib():
         L.mb_mfma_f32_16x16x4.argtypes = [vp, vp, vp, vp]
         L.mb_mfma_bf16_16x16x32.restype = ctypes.c_int
         L.mb_mfma_bf16_16x16x32.argtypes = [vp, vp, vp, vp]
+        L.mb_mfma_i8_16x16x64.restype = ctypes.c_int
+        L.mb_mfma_i8_16x16x64.argtypes = [vp, vp, vp, vp]
         L.mb_mfma_f64_4x4x4.restype = ctypes.c_int
         L.mb_mfma_f64_4x4x4.argtypes = [vp, vp, vp, vp, ctypes.c_int]
         L.mb_lds_probe.restype = ctypes.c_int
@@ -89,6 +91,19 @@ def mfma_bf16_once(a, b, c):
     torch.cuda.synchronize()
     assert lib().mb_mfma_bf16_16x16x32(ab[0].data_ptr(), ab[1].data_ptr(), ct.data_ptr(),
                                        d.data_ptr()) == 0
+    return d.cpu()
+
+
+def mfma_i8_once(a, b, c):
+    """One v_mfma_i32_16x16x64_i8: a, b (64, 16) int8 values, c (64, 4)
+    int32.  Returns (64, 4) int32."""
+    dev = torch.device("cuda")
+    ab = [torch.as_tensor(x, dtype=torch.int8).to(dev).contiguous() for x in (a, b)]
+    ct = torch.as_tensor(c, dtype=torch.int32).to(dev).contiguous()
+    d = torch.empty(64, 4, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    assert lib().mb_mfma_i8_16x16x64(ab[0].data_ptr(), ab[1].data_ptr(), ct.data_ptr(),
+                                     d.data_ptr()) == 0
     return d.cpu()
 
 

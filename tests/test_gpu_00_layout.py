@@ -85,3 +85,26 @@ def test_mfma_bf16_16x16x32_lane_layout():
     D = Am @ Bm + Cm
     want = np.stack([D[4 * (lanes // 16) + v, lanes % 16] for v in range(4)], axis=1)
     assert np.array_equal(d, want)
+
+
+def test_mfma_i8_16x16x64_lane_layout():
+    """v_mfma_i32_16x16x64_i8 (emulated mode on int8 digits): lane l holds
+    A(l%16, 16 (l/16) + e) and B(16 (l/16) + e, l%16) in byte e = 0..15 of
+    its 16-byte operand; result register v of lane l is D(4 (l/16) + v, l%16).
+    Extreme digits (-128, 127) included: products and sums are exact int32."""
+    from paper_2203_09353_amd import microbench
+    rng = np.random.default_rng(4)
+    Am = rng.integers(-128, 128, (16, 64))
+    Bm = rng.integers(-128, 128, (64, 16))
+    Am[0, :] = -128
+    Bm[:, 0] = -128
+    Am[1, :] = 127
+    Cm = rng.integers(-2 ** 20, 2 ** 20, (16, 16))
+    lanes = np.arange(64)
+    a = np.stack([Am[lanes % 16, 16 * (lanes // 16) + e] for e in range(16)], axis=1)
+    b = np.stack([Bm[16 * (lanes // 16) + e, lanes % 16] for e in range(16)], axis=1)
+    c = np.stack([Cm[4 * (lanes // 16) + v, lanes % 16] for v in range(4)], axis=1)
+    d = microbench.mfma_i8_once(a, b, c).numpy()
+    D = Am @ Bm + Cm
+    want = np.stack([D[4 * (lanes // 16) + v, lanes % 16] for v in range(4)], axis=1)
+    assert np.array_equal(d, want)
