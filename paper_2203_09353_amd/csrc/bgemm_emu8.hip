@@ -114,33 +114,47 @@ __device__ __forceinline__ void z_words(double v, int sh, unsigned& lo, unsigned
   }
 }
 
-// byte b of four words packed into one word (first word in the low byte)
-__device__ __forceinline__ unsigned pack_byte(unsigned w0, unsigned w1, unsigned w2, unsigned w3,
-                                              int b) {
-  const int sh = 8 * b;
-  return ((w0 >> sh) & 0xFFu) | (((w1 >> sh) & 0xFFu) << 8) | (((w2 >> sh) & 0xFFu) << 16) |
-         ((w3 >> sh) << 24);
+// 4 x 4 byte transpose: out[b] = [w0.b, w1.b, w2.b, w3.b] (first word in the
+// low byte), for the NB lowest bytes b.  v_perm_b32 picks bytes of
+// {src0 (high), src1 (low)}: selectors 0-3 address src1, 4-7 src0.
+template <int NB>
+__device__ __forceinline__ void transpose4(unsigned w0, unsigned w1, unsigned w2, unsigned w3,
+                                           unsigned (&out)[4]) {
+  const unsigned l01 = __builtin_amdgcn_perm(w1, w0, 0x05010400u);   // w0.0 w1.0 w0.1 w1.1
+  const unsigned l23 = __builtin_amdgcn_perm(w3, w2, 0x05010400u);   // w2.0 w3.0 w2.1 w3.1
+  out[0] = __builtin_amdgcn_perm(l23, l01, 0x05040100u);
+  if constexpr (NB > 1) out[1] = __builtin_amdgcn_perm(l23, l01, 0x07060302u);
+  if constexpr (NB > 2) {
+    const unsigned h01 = __builtin_amdgcn_perm(w1, w0, 0x07030602u); // w0.2 w1.2 w0.3 w1.3
+    const unsigned h23 = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
+    out[2] = __builtin_amdgcn_perm(h23, h01, 0x05040100u);
+    if constexpr (NB > 3) out[3] = __builtin_amdgcn_perm(h23, h01, 0x07060302u);
+  }
 }
 
 // 16 values (consecutive k) -> S digit planes, one 16-byte word each, at
 // dst + t * PLANE (t = 0 the most significant digit).
 template <int S>
 __device__ __forceinline__ void split16(const double (&v)[16], int sh, unsigned char* dst) {
-  unsigned lo[16], hi[16];
+  constexpr int NL = S < 4 ? S : 4, NH = S - NL;
+  u4 w[S];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) z_words<S>(v[j], sh, lo[j], hi[j]);
+  for (int q = 0; q < 4; ++q) {
+    unsigned lo[4], hi[4];
 #pragma unroll
-  for (int t = 0; t < S; ++t) {
-    const int byte = S - 1 - t;
-    u4 w;
+    for (int j = 0; j < 4; ++j) z_words<S>(v[4 * q + j], sh, lo[j], hi[j]);
+    unsigned bl[4], bh[4];
+    transpose4<NL>(lo[0], lo[1], lo[2], lo[3], bl);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const unsigned* src = byte < 4 ? lo : hi;
-      w[q] = pack_byte(src[4 * q], src[4 * q + 1], src[4 * q + 2], src[4 * q + 3], byte & 3) ^
-             0x80808080u;
+    for (int b = 0; b < NL; ++b) w[S - 1 - b][q] = bl[b] ^ 0x80808080u;
+    if constexpr (NH > 0) {
+      transpose4<NH>(hi[0], hi[1], hi[2], hi[3], bh);
+#pragma unroll
+      for (int b = 0; b < NH; ++b) w[S - 5 - b][q] = bh[b] ^ 0x80808080u;
     }
-    *(u4*)(dst + t * PLANE) = w;
   }
+#pragma unroll
+  for (int t = 0; t < S; ++t) *(u4*)(dst + t * PLANE) = w[t];
 }
 
 // ---- main kernel ----------------------------------------------------------
@@ -181,10 +195,11 @@ __global__ __launch_bounds__(NT, 2) void k_emu8(int M, int N, int K, double alph
   const int ar = tid & 63, akg = tid >> 6;
   const int bc = tid >> 2, bkq = tid & 3;
   const bool a_ok = m0 + ar < M, b_ok = n0 + bc < N;
-  const int ash = a_ok ? (8 * S - 2) - ea[inst * M + m0 + ar] : 0;
-  const int bsh = b_ok ? (8 * S - 2) - fb[inst * N + n0 + bc] : 0;
-  // out-of-range rows / columns read a valid address and are zeroed after
-  // the load, so every load of a step is issued before the first wait
+  // rows / columns outside the matrix get a shift that makes every value 0
+  const int ash = a_ok ? (8 * S - 2) - ea[inst * M + m0 + ar] : -4096;
+  const int bsh = b_ok ? (8 * S - 2) - fb[inst * N + n0 + bc] : -4096;
+  // out-of-range rows / columns read a valid address (row / column 0);
+  // every load of a step is issued before the first wait
   const AS_GLOBAL double* arow = A + (a_ok ? m0 + ar : 0);
   const AS_GLOBAL double* bcol = B + (int64_t)(b_ok ? n0 + bc : 0) * ldb;
   const bool b_vec = ((((uintptr_t)B) & 15) == 0) && ((ldb & 1) == 0);
@@ -204,20 +219,30 @@ __global__ __launch_bounds__(NT, 2) void k_emu8(int M, int N, int K, double alph
   for (int k0 = 0; k0 < K; k0 += BK) {
     double av[16], bv[16];
     const int ka = k0 + 16 * akg, kb = k0 + 16 * bkq;
+    if (k0 + BK <= K) {
+      // whole step inside k (uniform): plain loads; rows / columns outside
+      // the matrix read row / column 0 and their shift of -4096 zeroes them
+      const AS_GLOBAL double* pa = arow + (int64_t)ka * lda;
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      av[j] = keep(arow[(int64_t)min(ka + j, K - 1) * lda], a_ok && ka + j < K);
-    if (b_vec && k0 + BK <= K) {       // uniform: whole step in range, 16-byte aligned
-      const AS_GLOBAL d2* p = (const AS_GLOBAL d2*)(bcol + kb);
+      for (int j = 0; j < 16; ++j) av[j] = pa[(int64_t)j * lda];
+      if (b_vec) {
+        const AS_GLOBAL d2* p = (const AS_GLOBAL d2*)(bcol + kb);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const d2 x = p[j];
-        bv[2 * j] = b_ok ? x.x : 0.0;
-        bv[2 * j + 1] = b_ok ? x.y : 0.0;
+        for (int j = 0; j < 8; ++j) {
+          const d2 x = p[j];
+          bv[2 * j] = x.x;
+          bv[2 * j + 1] = x.y;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) bv[j] = bcol[kb + j];
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) bv[j] = keep(bcol[min(kb + j, K - 1)], b_ok && kb + j < K);
+      for (int j = 0; j < 16; ++j)
+        av[j] = keep(arow[(int64_t)min(ka + j, K - 1) * lda], ka + j < K);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) bv[j] = keep(bcol[min(kb + j, K - 1)], kb + j < K);
     }
     __syncthreads();   // the previous step's digit reads are done
     split16<S>(av, ash, la + ar * RS + 16 * akg);
