@@ -38,6 +38,10 @@
 namespace bg {
 
 typedef double d2 __attribute__((ext_vector_type(2)));
+// a pair of doubles at any 8-byte boundary: with an odd leading dimension
+// every other column's pairs start off a 16-byte boundary, and the memory
+// system serves such 16-byte accesses (unaligned access mode)
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
 // Explicit address spaces: matrices are global memory (address space 1),
 // operand tiles are LDS (address space 3).  Without them the compiler falls
@@ -148,7 +152,7 @@ struct OpLoader {
 
   // base: operand matrix; ld: its leading dimension; (c0, s0): tile origin
   // along the contiguous / strided dims; (cext, sext): matrix extents there.
-  // `fast`: the whole tile is inside the matrix and 16-byte aligned.
+  // `fast`: the whole tile is inside the matrix.
   __device__ __forceinline__ void load(gcptr base, int64_t ld, int c0, int s0, int cext, int sext,
                                        bool fast, int tid) {
     if (fast) {
@@ -156,7 +160,7 @@ struct OpLoader {
       for (int it = 0; it < PER; ++it) {
         const int e = 2 * (tid + it * NT);
         const int cc = e % T::LC, ss = e / T::LC;
-        v[it] = *(const AS_GLOBAL d2*)(base + (c0 + cc) + (int64_t)(s0 + ss) * ld);
+        v[it] = *(const AS_GLOBAL d2u*)(base + (c0 + cc) + (int64_t)(s0 + ss) * ld);
       }
     } else {
 #pragma unroll
@@ -537,8 +541,8 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
     const lptr la0 = lds, lb0 = lds + CF::NSTAGE * SM::A_ELEMS;
     const int a_cext = TA ? K : M, a_sext = TA ? M : K;
     const int b_cext = TB ? N : K, b_sext = TB ? K : N;
-    const bool a_vec = aligned16(A_) && (lda % 2 == 0) && (m0 + CF::BM <= M);
-    const bool b_vec = aligned16(B_) && (ldb % 2 == 0) && (n0 + CF::BN <= N);
+    const bool a_vec = m0 + CF::BM <= M;
+    const bool b_vec = n0 + CF::BN <= N;
     LA ra;
     LB rb;
     auto load = [&](int k0) {
