@@ -53,6 +53,10 @@ CANDIDATES = {
         "128,64,16,32,32,true,2,true",
         "64,128,16,32,32,true",
         "128,64,16,32,32,true,2,false,0,3",
+        "128,64,16,16,64,true,2,false,1",
+        "128,64,16,16,64,true,2,false,2",
+        "128,64,32,16,64,true",
+        "128,64,16,16,64,true,1",
     ]),
     "BG_CFGVB_M": ("vb", [
         "64,64,16,32,32,true,2,true",
