@@ -21,10 +21,10 @@
 // Every rounding is fixed in kind and order, so the result equals a CPU
 // implementation of these steps bit for bit.
 //
-// Main kernel: one 64 x 64 C tile per workgroup of four waves (2 x 2 blocks
-// of 16 x 16 each), 64 of k per step.  Each thread loads 16 binary64 values
-// of A (one row, 16 consecutive k) and 16 of B (one column, 16 consecutive
-// k), turns them into S digit bytes each and writes one 16-byte word per
+// Main kernel: one 128 x 64 C tile per workgroup of eight waves (each 32 x 32,
+// 2 x 2 blocks of 16 x 16), 64 of k per step.  Each thread loads 16 binary64
+// values of A (one row, 16 consecutive k) and 8 of B (one column, 8
+// consecutive k), turns them into S digit bytes each and writes one word per
 // digit plane to LDS (rows of 64 digits, 80-byte stride); then each wave runs
 // S (S + 1) / 2 x 4 int8 matrix-core instructions into S int32 accumulator
 // sets.  The instruction's first operand is B's digits and its second A's, so
@@ -41,11 +41,18 @@ namespace emu8 {
 typedef int i4 __attribute__((ext_vector_type(4)));
 #define AS_GLOBAL __attribute__((address_space(1)))
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
-constexpr int BM = 64, BN = 64, BK = 64, NT = 256;
+#ifndef BG_EMU8_BM
+#define BG_EMU8_BM 128
+#endif
+// C tile: TM x 64 (TM = 64: four waves; 128: eight waves), 64 of k per step
+constexpr int TM = BG_EMU8_BM, BN = 64, BK = 64, NT = TM * 4;
+static_assert(TM == 64 || TM == 128, "tile height");
 constexpr int RS = BK + 16;            // bytes per digit row in LDS
-constexpr int PLANE = 64 * RS;         // bytes per digit plane (64 rows)
+constexpr int PLANE_A = TM * RS;       // bytes per digit plane of A (TM rows)
+constexpr int PLANE_B = 64 * RS;       // bytes per digit plane of B (64 columns)
 constexpr int EXP_COLS = 16;           // columns of B per exponent block
 
 // ---- exponents ------------------------------------------------------------
@@ -132,14 +139,14 @@ __device__ __forceinline__ void transpose4(unsigned w0, unsigned w1, unsigned w2
   }
 }
 
-// 16 values (consecutive k) -> S digit planes, one 16-byte word each, at
-// dst + t * PLANE (t = 0 the most significant digit).
-template <int S>
-__device__ __forceinline__ void split16(const double (&v)[16], int sh, unsigned char* dst) {
-  constexpr int NL = S < 4 ? S : 4, NH = S - NL;
-  u4 w[S];
+// NV values (consecutive k, NV = 8 or 16) -> S digit planes, one NV-byte word
+// each, at dst + t * plane (t = 0 the most significant digit).
+template <int S, int NV>
+__device__ __forceinline__ void split(const double (&v)[NV], int sh, unsigned char* dst, int plane) {
+  constexpr int NL = S < 4 ? S : 4, NH = S - NL, NQ = NV / 4;
+  unsigned w[S][NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     unsigned lo[4], hi[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) z_words<S>(v[4 * q + j], sh, lo[j], hi[j]);
@@ -154,7 +161,10 @@ __device__ __forceinline__ void split16(const double (&v)[16], int sh, unsigned 
     }
   }
 #pragma unroll
-  for (int t = 0; t < S; ++t) *(u4*)(dst + t * PLANE) = w[t];
+  for (int t = 0; t < S; ++t) {
+    if constexpr (NQ == 4) *(u4*)(dst + t * plane) = u4{w[t][0], w[t][1], w[t][2], w[t][3]};
+    else *(u2*)(dst + t * plane) = u2{w[t][0], w[t][1]};
+  }
 }
 
 // ---- main kernel ----------------------------------------------------------
@@ -177,23 +187,24 @@ __global__ __launch_bounds__(NT, 2) void k_emu8(int M, int N, int K, double alph
                                                 int64_t per_xcd) {
   // every binary64 rounding below is the one written (no fused multiply-add)
 #pragma clang fp contract(off)
-  __shared__ __align__(16) unsigned char lds[2 * S * PLANE];
+  __shared__ __align__(16) unsigned char lds[S * (PLANE_A + PLANE_B)];
   unsigned char* la = lds;
-  unsigned char* lb = lds + S * PLANE;
+  unsigned char* lb = lds + S * PLANE_A;
   const int64_t bid = blockIdx.x;
   const int64_t id = (bid % 8) * per_xcd + bid / 8;   // contiguous tiles per XCD
   if (id >= total_tiles) return;
   const int64_t inst = id / tiles_per_inst;
   const int tt = (int)(id - inst * tiles_per_inst);
-  const int m0 = (tt % tiles_m) * BM, n0 = (tt / tiles_m) * BN;
+  const int m0 = (tt % tiles_m) * TM, n0 = (tt / tiles_m) * BN;
   const AS_GLOBAL double* A = (const AS_GLOBAL double*)Ap[inst];
   const AS_GLOBAL double* B = (const AS_GLOBAL double*)Bp[inst];
   AS_GLOBAL double* C = (AS_GLOBAL double*)Cp[inst];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // split roles: A row m0 + ar, k = 16 akg .. +15; B column n0 + bc, k = 16 bkq .. +15
-  const int ar = tid & 63, akg = tid >> 6;
-  const int bc = tid >> 2, bkq = tid & 3;
+  // split roles: A row m0 + ar, k = 16 akg .. +15; B column n0 + bc, k = BV bkq .. +BV-1
+  constexpr int BV = 64 * 64 / NT;     // B values per thread: 16 (TM 64) or 8 (TM 128)
+  const int ar = tid % TM, akg = tid / TM;
+  const int bc = tid / (64 / BV), bkq = tid % (64 / BV);
   const bool a_ok = m0 + ar < M, b_ok = n0 + bc < N;
   // rows / columns outside the matrix get a shift that makes every value 0
   const int ash = a_ok ? (8 * S - 2) - ea[inst * M + m0 + ar] : -4096;
@@ -205,7 +216,7 @@ __global__ __launch_bounds__(NT, 2) void k_emu8(int M, int N, int K, double alph
   const bool b_vec = ((((uintptr_t)B) & 15) == 0) && ((ldb & 1) == 0);
 
   // wave tile: rows wm0 .. +31, columns wn0 .. +31 of the C tile
-  const int wm0 = (wave & 1) * 32, wn0 = (wave >> 1) * 32;
+  const int wm0 = (wave % (TM / 32)) * 32, wn0 = (wave / (TM / 32)) * 32;
   const int li = lane & 15, lg = lane >> 4;
 
   i4 acc[S][2][2];
@@ -217,8 +228,8 @@ __global__ __launch_bounds__(NT, 2) void k_emu8(int M, int N, int K, double alph
       for (int bj = 0; bj < 2; ++bj) acc[g][bi][bj] = i4{0, 0, 0, 0};
 
   for (int k0 = 0; k0 < K; k0 += BK) {
-    double av[16], bv[16];
-    const int ka = k0 + 16 * akg, kb = k0 + 16 * bkq;
+    double av[16], bv[BV];
+    const int ka = k0 + 16 * akg, kb = k0 + BV * bkq;
     if (k0 + BK <= K) {
       // whole step inside k (uniform): plain loads; rows / columns outside
       // the matrix read row / column 0 and their shift of -4096 zeroes them
@@ -228,25 +239,25 @@ __global__ __launch_bounds__(NT, 2) void k_emu8(int M, int N, int K, double alph
       if (b_vec) {
         const AS_GLOBAL d2* p = (const AS_GLOBAL d2*)(bcol + kb);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < BV / 2; ++j) {
           const d2 x = p[j];
           bv[2 * j] = x.x;
           bv[2 * j + 1] = x.y;
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) bv[j] = bcol[kb + j];
+        for (int j = 0; j < BV; ++j) bv[j] = bcol[kb + j];
       }
     } else {
 #pragma unroll
       for (int j = 0; j < 16; ++j)
         av[j] = keep(arow[(int64_t)min(ka + j, K - 1) * lda], ka + j < K);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) bv[j] = keep(bcol[min(kb + j, K - 1)], kb + j < K);
+      for (int j = 0; j < BV; ++j) bv[j] = keep(bcol[min(kb + j, K - 1)], kb + j < K);
     }
     __syncthreads();   // the previous step's digit reads are done
-    split16<S>(av, ash, la + ar * RS + 16 * akg);
-    split16<S>(bv, bsh, lb + bc * RS + 16 * bkq);
+    split<S, 16>(av, ash, la + ar * RS + 16 * akg, PLANE_A);
+    split<S, BV>(bv, bsh, lb + bc * RS + BV * bkq, PLANE_B);
     __syncthreads();
 
     i4 af[S][2];
@@ -254,13 +265,13 @@ __global__ __launch_bounds__(NT, 2) void k_emu8(int M, int N, int K, double alph
     for (int t = 0; t < S; ++t)
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
-        af[t][bi] = *(const i4*)(la + t * PLANE + (wm0 + 16 * bi + li) * RS + 16 * lg);
+        af[t][bi] = *(const i4*)(la + t * PLANE_A + (wm0 + 16 * bi + li) * RS + 16 * lg);
 #pragma unroll
     for (int u = 0; u < S; ++u) {
       i4 bf[2];
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj)
-        bf[bj] = *(const i4*)(lb + u * PLANE + (wn0 + 16 * bj + li) * RS + 16 * lg);
+        bf[bj] = *(const i4*)(lb + u * PLANE_B + (wn0 + 16 * bj + li) * RS + 16 * lg);
 #pragma unroll
       for (int t = 0; t + u < S; ++t)
 #pragma unroll
@@ -304,7 +315,7 @@ static hipError_t launch_group(const UniformArgs& a, int64_t b0, int g, int* ea,
   const int per_inst = nb_a + nb_b;
   hipLaunchKernelGGL(k_exp, dim3((unsigned)((int64_t)per_inst * g)), dim3(256), 0, s, a.m, a.n,
                      a.k, a.A + b0, a.lda, a.B + b0, a.ldb, ea, fb, nb_a, per_inst);
-  const int tiles_m = (a.m + BM - 1) / BM, tiles_n = (a.n + BN - 1) / BN;
+  const int tiles_m = (a.m + TM - 1) / TM, tiles_n = (a.n + BN - 1) / BN;
   const int64_t tpi = (int64_t)tiles_m * tiles_n;
   const int64_t total = tpi * g;
   const int64_t per_xcd = (total + 7) / 8;
@@ -318,7 +329,7 @@ template <int S>
 static hipError_t launch(const UniformArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
   const int64_t per = (int64_t)(a.m + a.n) * (int64_t)sizeof(int);
   int64_t gmax = (int64_t)(ws_bytes / (size_t)per);
-  const int tiles_m = (a.m + BM - 1) / BM, tiles_n = (a.n + BN - 1) / BN;
+  const int tiles_m = (a.m + TM - 1) / TM, tiles_n = (a.n + BN - 1) / BN;
   const int64_t tpi = (int64_t)tiles_m * tiles_n;
   const int nb = (a.m + 255) / 256 + (a.n + EXP_COLS - 1) / EXP_COLS;
   // grid sizes stay within 32 bits
