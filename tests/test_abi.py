@@ -95,3 +95,15 @@ def test_argument_rules_match_oracle():
             o = oracle.check_args(ta, tb, m, n, k, lda, ldb, ldc)
             g = bgemm.check_batched_args(ta, tb, m, n, k, P, lda, P, ldb, P, ldc, 1)
             assert -o == g, (ta, tb, m, n, k, lda, ldb, ldc)
+
+
+def test_missing_library_fails_loudly():
+    # no fallback: without the built HIP library every entry point raises
+    from paper_2203_09353_amd import bgemm
+    saved = bgemm._lib
+    bgemm._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="not built"):
+            bgemm.lib("/nonexistent/libbgemm.so")
+    finally:
+        bgemm._lib = saved
