@@ -316,6 +316,21 @@ def serving_bench(args, h):
             sw[mode] = {"seconds": round(secs, 4), "gflops": round(fl / secs / 1e9, 1)}
         sw["graph_speedup"] = round(sw["eager"]["seconds"] / sw["graph"]["seconds"], 3)
         log("sweeps: " + json.dumps(sw))
+        # the same sweeps for 64 clients of 32 x 32 states, where each launch
+        # is short and the launch cost shows
+        small = serve.Server(h, [32] * clients, seed=seed + 1)
+        try:
+            sws = {}
+            for mode in ("eager", "graph"):
+                small.sweeps(2, 16, graph=(mode == "graph"))     # warm-up
+                small.reset()
+                secs = small.sweeps(100, 16, graph=(mode == "graph"))
+                fl = 2.0 * 32 ** 3 * clients * 16 * 100
+                sws[mode] = {"seconds": round(secs, 5), "gflops": round(fl / secs / 1e9, 1)}
+            sws["graph_speedup"] = round(sws["eager"]["seconds"] / sws["graph"]["seconds"], 3)
+            log("sweeps, 32 x 32 states: " + json.dumps(sws))
+        finally:
+            small.close()
         srv.reset()
         srv.run(a, c, l)
         # parity: one client of the last run against the CPU replay
@@ -358,7 +373,7 @@ def serving_bench(args, h):
                       "state_sizes": sorted(set(int(x) for x in sizes)),
                       "duration_s": args.duration},
            "roofline": roof, "cpu_baseline": cpu, "rates": rows, "one_at_a_time": serial,
-           "sweeps_100x16": sw,
+           "sweeps_100x16": sw, "sweeps_100x16_32x32_states": sws,
            "batching_gain": round(top["achieved_req_s"] / serial["achieved_req_s"], 2),
            "parity_rel_fro_one_client": parity}
     print(json.dumps(out), flush=True)
