@@ -3,7 +3,7 @@
     python bench.py [--steps K] [--warmup W] [--workload config2+vb]
     python bench.py --workload config4 [--modes fp64,fp32,bf16,emu3,emu6,emu7,i8emu6,i8emu7,i8emu8]
     python bench.py --workload config5 [--rates 1000,5000,20000,50000] [--duration 2]
-    python bench.py --workload gram15 [--steps K]
+    python bench.py --workload gram15|gram21 [--steps K]
     python bench.py --workload gate21 [--steps K]
 
 A step is one pass over every part of the workload: the three uniform
@@ -27,7 +27,8 @@ p50 / p99 request latency; ``value`` is the GFLOP/s at the highest rate.
 ``--workload gram15`` times the complex batched GEMM on the paper's
 entanglement-entropy product: 10,000 Hermitian Gram products C = Psi Psi^H
 with Psi of 2^8 x 2^7 complex entries (S = 15 spins), binary64, counting
-8 m n k real flops per instance.
+8 m n k real flops per instance; ``--workload gram21`` the same for 64
+products with Psi of 2^11 x 2^10 (S = 21), checked on sampled rows of C.
 
 ``--workload gate21`` times the two-spin gate on 64 states of S = 21 spins
 (2^21 binary64 complex amplitudes each, 32 MiB), a new seeded site and gate
@@ -379,14 +380,18 @@ def serving_bench(args, h):
     print(json.dumps(out), flush=True)
 
 
-def gram_bench(args, h):
-    """The gram15 line: C_i = Psi_i Psi_i^H, Psi_i 256 x 128 complex."""
+GRAM = {15: 10_000, 21: 64}     # spins S -> instances of the Gram product
+
+
+def gram_bench(args, h, S=15):
+    """The gram<S> line: C_i = Psi_i Psi_i^H, Psi_i of 2^ceil(S/2) x
+    2^floor(S/2) complex (256 x 128 at S = 15, 2048 x 1024 at S = 21)."""
     import numpy as np
     import torch
     import oracle
     from paper_2203_09353_amd import inputs, bgemm as bg
 
-    batch, rows, cols = 10_000, 256, 128
+    batch, rows, cols = GRAM[S], 2 ** ((S + 1) // 2), 2 ** (S // 2)
     seed = 6
     re = torch.empty(batch, cols, rows, dtype=torch.float64, device="cuda")
     im = torch.empty_like(re)
@@ -411,11 +416,14 @@ def gram_bench(args, h):
     launch()
     torch.cuda.synchronize()
     worst = 0.0
+    nsel = min(rows, 16)      # sampled rows of C: the oracle on those rows of Psi
     for i in inputs.permutation(11, 6, batch)[:max(1, args.check)].tolist():
-        P = Psi[i].cpu().numpy()[None]
-        ref = np.zeros((1, rows, rows), dtype=np.complex128)
-        oracle.zgemm_batched("N", "C", rows, rows, cols, 1.0, P, P, 0.0, ref)
-        got = C[i].cpu().numpy()
+        P = Psi[i].cpu().numpy()                                     # (cols, rows) storage
+        sel = np.sort(inputs.permutation(13, i, rows)[:nsel].numpy())
+        Psel = np.ascontiguousarray(P[:, sel])                       # nsel x cols, column-major
+        ref = np.zeros((1, rows, nsel), dtype=np.complex128)         # nsel x rows result
+        oracle.zgemm_batched("N", "C", nsel, rows, cols, 1.0, Psel[None], P[None], 0.0, ref)
+        got = C[i].cpu().numpy()[:, sel]                             # rows sel of C
         worst = max(worst, float(np.linalg.norm(got - ref[0]) / np.linalg.norm(ref[0])))
     log("sampled parity (max rel Frobenius): %.3e" % worst)
     for _ in range(args.warmup):
@@ -436,30 +444,51 @@ def gram_bench(args, h):
     tf = flops / (ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": round(tf * 1e12 / PEAK_FP64, 4), "traffic": None,
-            "kernel": "k_zgemm (N, C) 256 x 256 x 128 complex"}
+            "kernel": "k_zgemm (N, C) %d x %d x %d complex" % (rows, rows, cols)}
     cpu = None
     if not args.no_cpu:
         log("timing the complex oracle on a sample")
         threads = len(os.sched_getaffinity(0))
-        n = 1
-        while True:
-            P = Psi[:n].cpu().numpy()
-            ref = np.zeros((n, rows, rows), dtype=np.complex128)
-            t1 = time.perf_counter()
-            oracle.zgemm_batched("N", "C", rows, rows, cols, 1.0, P, P, 0.0, ref, nthreads=threads)
-            t = time.perf_counter() - t1
-            if t > args.cpu_seconds / 4 or n >= batch:
-                break
-            n = min(batch, n * 4)
-        cpu = {"value": round(8.0 * rows * rows * cols * n / t / 1e9, 3), "unit": "GFLOP/s",
-               "cores": threads, "kind": "oracle",
-               "sample": "first %d of %d instances, %.1f s" % (n, batch, t)}
+        if rows <= 256:
+            n = 1
+            while True:
+                P = Psi[:n].cpu().numpy()
+                ref = np.zeros((n, rows, rows), dtype=np.complex128)
+                t1 = time.perf_counter()
+                oracle.zgemm_batched("N", "C", rows, rows, cols, 1.0, P, P, 0.0, ref,
+                                     nthreads=threads)
+                t = time.perf_counter() - t1
+                if t > args.cpu_seconds / 4 or n >= batch:
+                    break
+                n = min(batch, n * 4)
+            cpu = {"value": round(8.0 * rows * rows * cols * n / t / 1e9, 3), "unit": "GFLOP/s",
+                   "cores": min(threads, n), "kind": "oracle",
+                   "sample": "first %d of %d instances, %.1f s" % (n, batch, t)}
+        else:
+            # one instance is too long for the time box: the first r rows of
+            # C of the first instance, r doubling until the time box is used
+            P = Psi[0].cpu().numpy()
+            r = 16
+            while True:
+                Psel = np.ascontiguousarray(P[:, :r])
+                ref = np.zeros((1, rows, r), dtype=np.complex128)
+                t1 = time.perf_counter()
+                oracle.zgemm_batched("N", "C", r, rows, cols, 1.0, Psel[None], P[None], 0.0, ref,
+                                     nthreads=threads)
+                t = time.perf_counter() - t1
+                if t > args.cpu_seconds / 4 or r >= rows:
+                    break
+                r = min(rows, r * 2)
+            # the oracle parallelises over instances: one instance, one thread
+            cpu = {"value": round(8.0 * r * rows * cols / t / 1e9, 3), "unit": "GFLOP/s",
+                   "cores": 1, "kind": "oracle",
+                   "sample": "first %d of %d rows of C of one instance, %.1f s" % (r, rows, t)}
     out = {"metric": METRIC, "value": round(flops / (ms * 1e-3) / 1e9, 1), "unit": "GFLOP/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
            "wall_ms_per_step": round(wall * 1e3, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "c128 (f64 pairs)",
            "data": "synthetic (seeded counter-based uniform[-1,1) real and imaginary parts)",
-           "config": {"workload": "gram15", "instances": batch, "psi": [rows, cols],
+           "config": {"workload": "gram%d" % S, "instances": batch, "psi": [rows, cols],
                       "op": "C = Psi Psi^H"},
            "roofline": roof, "cpu_baseline": cpu, "parity_max_rel_fro": worst}
     print(json.dumps(out), flush=True)
@@ -653,8 +682,8 @@ def main():
     if args.workload == "config5":
         serving_bench(args, h)
         return
-    if args.workload == "gram15":
-        gram_bench(args, h)
+    if args.workload in ("gram15", "gram21"):
+        gram_bench(args, h, int(args.workload[4:]))
         return
     if args.workload == "gate21":
         gate_bench(args, h)
