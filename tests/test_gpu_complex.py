@@ -146,3 +146,21 @@ def test_complex_argument_errors(h):
     with pytest.raises(bgemm.BgemmError) as e:
         h.zbatched(A, A, A.clone(), 9, 8, 8, 1.0, 0.0, "N", "N")
     assert e.value.arg == 8
+
+
+def test_hermitian_gram_s21_sampled_rows(h):
+    # S = 21: Psi 2048 x 1024; 16 sampled rows of C against the oracle on
+    # those rows of Psi (the same definition restricted to the rows)
+    rows, cols = 2048, 1024
+    Psi = _zbatch(7, 0, 1, rows, cols, rows)
+    Pd = Psi.cuda()
+    Cd = torch.zeros(1, rows, rows, dtype=torch.complex128, device="cuda")
+    h.zbatched(Pd, Pd, Cd, rows, rows, cols, 1.0, 0.0, "N", "C")
+    torch.cuda.synchronize()
+    P = Psi.numpy()[0]
+    sel = np.sort(np.random.default_rng(3).choice(rows, 16, replace=False))
+    ref = np.zeros((1, rows, 16), dtype=np.complex128)
+    oracle.zgemm_batched("N", "C", 16, rows, cols, 1.0, np.ascontiguousarray(P[:, sel])[None],
+                         P[None], 0.0, ref)
+    got = Cd.cpu().numpy()[0][:, sel]
+    assert np.linalg.norm(got - ref[0]) <= 1e-13 * np.linalg.norm(ref[0])
