@@ -52,6 +52,33 @@ def part_of(kernel_name: str, order: int) -> str:
     return "other"
 
 
+def durations_by_part(path: str) -> dict:
+    """Average device time per launch of each part from a --kernel-trace CSV:
+    dispatches in start order; the 128-tile uniform launches alternate u256,
+    s512 (the benchmark's part order); a variable-size launch is its planning
+    kernels plus one persistent kernel per class."""
+    rows = [r for r in _rows(path) if "bg::" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    tot, launches = {}, {}
+    big = 0
+    for r in rows:
+        name = r["Kernel_Name"]
+        ms = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        if "k_vb_" in name:
+            p = "vb"
+            if "k_vb_count" in name:
+                launches["vb"] = launches.get("vb", 0) + 1
+        else:
+            order = 0
+            if "k_uniform" in name and "Cfg<64, 64" not in name and "Cfg<32, 32" not in name:
+                order = big % 2
+                big += 1
+            p = part_of(name, order)
+            launches[p] = launches.get(p, 0) + 1
+        tot[p] = tot.get(p, 0.0) + ms
+    return {p: (launches.get(p, 0), tot[p] / max(1, launches.get(p, 0))) for p in tot}
+
+
 def counter_by_part(path: str, counter: str) -> dict:
     out = {}
     rows = [r for r in _rows(path) if r["Counter_Name"] == counter]
@@ -71,6 +98,7 @@ def counter_by_part(path: str, counter: str) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", required=True)
+    ap.add_argument("--trace", help="kernel-trace CSV of the same run (per-part durations)")
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--copy-fetch", required=True)
@@ -99,6 +127,14 @@ def main():
         name = r["Name"].split("(")[0]
         lines.append("| `%s` | %s | %.3f | %.3f |" % (name, r["Calls"], float(r["AverageNs"]) / 1e6,
                                                      float(r["TotalDurationNs"]) / 1e6))
+    if a.trace:
+        per = durations_by_part(a.trace)
+        lines += ["", "Per part (device time of its kernels per launch; the two 128-tile uniform "
+                  "launches of a step are u256 then s512):", "",
+                  "| part | launches | average ms per launch |", "|---|---:|---:|"]
+        for p in ("u32", "u64", "u256", "s512", "vb"):
+            if p in per:
+                lines.append("| %s | %d | %.3f |" % (p, per[p][0], per[p][1]))
     lines += ["", "## HBM traffic per launch (--pmc FETCH_SIZE, --pmc WRITE_SIZE)", "",
               "Copy-kernel calibration on %d bytes each way: FETCH_SIZE x %.4f, WRITE_SIZE x %.4f "
               "(counter KiB -> bytes)." % (a.copy_bytes, fetch_factor, write_factor), "",
