@@ -142,3 +142,19 @@ def test_sweeps_then_requests_continue_the_same_chain(h):
         assert np.linalg.norm(S - ref) <= 1e-12 * np.linalg.norm(ref)
     finally:
         srv.close()
+
+
+def test_sweeps_argument_errors_and_zero_sweeps(h):
+    srv = serve.Server(h, SIZES, seed=31)
+    try:
+        for sw, ch in ((-1, 2), (1, 0)):
+            with pytest.raises(bgemm.BgemmError) as e:
+                srv.sweeps(sw, ch, graph=False)
+            assert e.value.status == 1
+        for graph in (False, True):
+            srv.sweeps(0, 3, graph=graph)            # nothing replayed
+            for cl, n in enumerate(SIZES):
+                S, p = srv.state(cl)
+                assert p == 0 and np.array_equal(S, np.eye(n))
+    finally:
+        srv.close()
