@@ -13,7 +13,13 @@
  * stored m x k (lda >= max(1, m)); with 'T' it is stored k x m
  * (lda >= max(1, k)).  B with 'N' is stored k x n (ldb >= max(1, k)); with 'T'
  * n x k (ldb >= max(1, n)).  ldc >= max(1, m).  Rows r >= rows of a column
- * (the ld padding) are never read or written.
+ * (the ld padding) are never written, and their values never reach a stored
+ * result.  They may be read: when a leading dimension is even and the
+ * column length odd, a 16-byte load at the end of a column can take the
+ * first padding element with it; that element only enters products for C
+ * rows or columns outside C, which are discarded.  The padding must therefore
+ * be readable memory (it is, by ld >= rows), but its contents (NaN included)
+ * never matter.
  *
  * Memory and ownership.  Matrices, the pointer arrays dA/dB/dC (one device
  * pointer per instance), the per-instance size arrays of the variable-size

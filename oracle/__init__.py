@@ -11,7 +11,9 @@ Matrices are numpy float64 arrays in the shape convention of
 dimension ``ld`` is an array of shape ``(cols, ld)``; a uniform batch is
 ``(batch, cols, ld)``.  Arrays must be C-contiguous.
 
-Parity status of each function: pinned (see tests/test_oracle_pins.py).
+Parity status of each function: pinned (real GEMM: tests/test_oracle_pins.py and
+tests/test_oracle_mutants.py; complex GEMM: tests/test_oracle_complex.py, and the
+batched complex wrapper: tests/test_oracle_zgemm_batched.py).
 """
 from __future__ import annotations
 

@@ -32,9 +32,7 @@ def lib():
         L.mb_mfma_i8_16x16x64.restype = ctypes.c_int
         L.mb_mfma_i8_16x16x64.argtypes = [vp, vp, vp, vp]
         L.mb_mfma_f64_4x4x4.restype = ctypes.c_int
-        L.mb_mfma_f64_4x4x4.argtypes = [vp, vp, vp, vp, ctypes.c_int]
-        L.mb_lds_probe.restype = ctypes.c_int
-        L.mb_lds_probe.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, vp]
+        L.mb_mfma_f64_4x4x4.argtypes = [vp, vp, vp, vp]
         L.mb_fp64_peak_ms.restype = ctypes.c_double
         L.mb_fp64_peak_ms.argtypes = [ctypes.c_int] * 4 + [vp]
         L.mb_stream_ms.restype = ctypes.c_double
@@ -57,15 +55,15 @@ def mfma_once(a, b, c):
     return d.cpu()
 
 
-def mfma4_once(a, b, c, mode=0):
-    """One v_mfma_f64_4x4x4_4b_f64 with broadcast mode (see microbench.hip);
-    a, b, c: 64 per-lane values.  Returns the 64 results."""
+def mfma4_once(a, b, c):
+    """One v_mfma_f64_4x4x4_4b_f64; a, b, c: 64 per-lane values.  Returns the
+    64 results."""
     dev = torch.device("cuda")
     t = [torch.as_tensor(x, dtype=torch.float64).to(dev).contiguous() for x in (a, b, c)]
     d = torch.empty(64, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     assert lib().mb_mfma_f64_4x4x4(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(),
-                                   d.data_ptr(), int(mode)) == 0
+                                   d.data_ptr()) == 0
     return d.cpu()
 
 
@@ -108,8 +106,9 @@ def mfma_i8_once(a, b, c):
 
 
 def fp64_peak_tflops(kind: str, grid: int | None = None, iters: int = 4000, reps: int = 5):
-    """kind: 'mfma' (4 chains), 'mfma8' (8 chains), 'valu', 'mixed'."""
-    code = {"mfma": 0, "valu": 1, "mixed": 2, "mfma8": 3, "mfma4x4": 4}[kind]
+    """kind: 'mfma' (16x16x4, 4 chains), 'mfma8' (8 chains), 'mfma4x4'
+    (4x4x4, 8 chains), 'valu' (vector FMA)."""
+    code = {"mfma": 0, "valu": 1, "mfma8": 3, "mfma4x4": 4}[kind]
     props = torch.cuda.get_device_properties(0)
     grid = grid or props.multi_processor_count * 8
     sink = torch.zeros(256, dtype=torch.float64, device="cuda")
@@ -120,56 +119,42 @@ def fp64_peak_tflops(kind: str, grid: int | None = None, iters: int = 4000, reps
         flop = waves * iters * chains * 2048.0
     elif code == 4:
         flop = waves * iters * 8 * 512.0
-    elif code == 1:
-        flop = waves * iters * 8 * 64 * 2.0
     else:
-        half = waves / 2
-        flop = half * iters * 4 * 2048.0 + half * iters * 8 * 8 * 64 * 2.0
+        flop = waves * iters * 8 * 64 * 2.0
     return flop * reps / (ms * 1e-3) / 1e12, ms
 
 
+STREAM_KINDS = {"copy_stride": 0, "read_stride": 1, "copy": 2, "read": 3, "copy_nt": 4,
+                "read_nt": 5}
+
+
 def stream_gbps(kind: str, nbytes: int = 4 << 30, grid: int | None = None, reps: int = 10):
-    """kind: 'copy' (reports read + write bytes) or 'read'."""
+    """HBM stream bandwidth in GB/s (copies count read + write bytes).  kind:
+    'copy' / 'read' (one 32 KB chunk per workgroup), '..._nt' (nontemporal),
+    '..._stride' (grid-stride loop over CUs x 16 workgroups)."""
+    code = STREAM_KINDS[kind]
     props = torch.cuda.get_device_properties(0)
     grid = grid or props.multi_processor_count * 16
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src) if kind == "copy" else src
+    dst = torch.empty_like(src) if code % 2 == 0 else src
     sink = torch.zeros(256, dtype=torch.float64, device="cuda")
-    ms = lib().mb_stream_ms(0 if kind == "copy" else 1, src.data_ptr(), dst.data_ptr(), nbytes,
-                            grid, reps, sink.data_ptr())
-    quad = 4 * grid * 256 * 16
+    ms = lib().mb_stream_ms(code, src.data_ptr(), dst.data_ptr(), nbytes, grid, reps,
+                            sink.data_ptr())
+    if ms <= 0:
+        raise RuntimeError("mb_stream_ms failed")
+    quad = (256 * 8 if code >= 2 else 4 * grid * 256) * 16
     nbytes = nbytes // quad * quad
-    moved = nbytes * (2 if kind == "copy" else 1) * reps
+    moved = nbytes * (2 if code % 2 == 0 else 1) * reps
     del src, dst
     return moved / (ms * 1e-3) / 1e9, ms
-
-
-LDS_KINDS = {"read_b64": (0, 8), "read_b128": (1, 16), "write_b64": (2, 8), "write_b128": (3, 16)}
-
-
-def lds_cycles(offsets, kind: str, iters: int = 2000) -> float:
-    """Shader clock cycles per LDS instruction of `kind` when lane l accesses
-    byte offset offsets[l] (one wave, eight independent instructions in
-    flight between waits)."""
-    code, width = LDS_KINDS[kind]
-    offs = [int(o) for o in offsets]
-    if len(offs) != 64 or any(o < 0 or o > 8192 - width or o % width for o in offs):
-        raise ValueError("64 offsets in [0, 8192 - width], multiples of the width")
-    d = torch.tensor(offs, dtype=torch.int32, device="cuda")
-    cyc = torch.zeros(1, dtype=torch.int64, device="cuda")
-    sink = torch.zeros(64, dtype=torch.int32, device="cuda")
-    for _ in range(2):
-        if lib().mb_lds_probe(code, d.data_ptr(), iters, cyc.data_ptr(), sink.data_ptr()) != 0:
-            raise RuntimeError("mb_lds_probe failed")
-    return float(cyc.item()) / (8 * iters)
 
 
 def summary():
     out = {"device": torch.cuda.get_device_name(0),
            "cus": torch.cuda.get_device_properties(0).multi_processor_count}
-    for k in ("mfma", "mfma8", "mfma4x4", "valu", "mixed"):
+    for k in ("mfma", "mfma8", "mfma4x4", "valu"):
         out["fp64_%s_tflops" % k] = round(fp64_peak_tflops(k)[0], 2)
-    for k in ("copy", "read"):
+    for k in STREAM_KINDS:
         out["hbm_%s_gbps" % k] = round(stream_gbps(k)[0], 1)
     return out
 
