@@ -1,10 +1,11 @@
 """Benchmark of the batched FP64 GEMM hot path on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload config2+vb]
-    python bench.py --workload config4 [--modes fp64,fp32,bf16,emu3,emu6,emu7,i8emu6,i8emu7,i8emu8]
+    python bench.py --workload config4 [--modes fp64,fp32,bf16,emu3,emu6,emu7,f32emu3,f32emu6,i8emu6,...]
     python bench.py --workload config5 [--rates 1000,5000,20000,50000] [--duration 2]
     python bench.py --workload gram15|gram21 [--steps K]
     python bench.py --workload gate21 [--steps K]
+    python bench.py --workload config1|vb8 [--cold]
 
 A step is one pass over every part of the workload: the three uniform
 batches of 64^3, 256^3 and 512^3 (symmetric) instances through
@@ -22,13 +23,22 @@ mode that reaches binary64 accuracy (relative Frobenius error <= 1e-13).
 clients with states of 2^k x 2^k (k uniform in 5..9), Poisson arrivals at each
 offered rate for ``--duration`` seconds, chains of 1..16 products whose
 factors are generated on the device; per rate the achieved GFLOP/s and the
-p50 / p99 request latency; ``value`` is the GFLOP/s at the highest rate.
+p50 / p99 request latency, under continuous batching and, on the same
+arrivals, in lock-step rounds (the paper's batched approach); ``value`` is the
+continuous-batching GFLOP/s at the highest rate.
 
 ``--workload gram15`` times the complex batched GEMM on the paper's
 entanglement-entropy product: 10,000 Hermitian Gram products C = Psi Psi^H
 with Psi of 2^8 x 2^7 complex entries (S = 15 spins), binary64, counting
 8 m n k real flops per instance; ``--workload gram21`` the same for 64
 products with Psi of 2^11 x 2^10 (S = 21), checked on sampled rows of C.
+
+``--workload config1`` (1000 x 32^3, beta 0) and ``--workload vb8`` (the
+variable-size batch with leading dimensions padded to multiples of 8) are
+secondary lines over one part; with ``--cold`` (the default for config1) each
+part is also timed with the last-level cache flushed before every launch
+(``ms_cold``, ``roofline_frac_cold``), since config1's 24.6 MB of operands
+otherwise stay cache-resident between launches.
 
 ``--workload gate21`` times the two-spin gate on 64 states of S = 21 spins
 (2^21 binary64 complex amplitudes each, 32 MiB), a new seeded site and gate
@@ -91,13 +101,15 @@ def part_launch(h, p):
 
 
 def parse_mode(name: str):
-    """'fp64' | 'fp32' | 'bf16' | 'emu<s>' | 'i8emu<s>' -> (bg_mode_t value,
+    """'fp64' | 'fp32' | 'bf16' | 'emu<s>' | 'i8emu<s>' | 'f32emu<s>' -> (bg_mode_t value,
     slices)."""
     fixed = {"fp64": (0, 0), "fp32": (1, 0), "bf16": (2, 0)}
     if name in fixed:
         return fixed[name]
     if name.startswith("emu") and name[3:].isdigit() and 1 <= int(name[3:]) <= 8:
         return (3, int(name[3:]))
+    if name.startswith("f32emu") and name[6:].isdigit() and 1 <= int(name[6:]) <= 8:
+        return (5, int(name[6:]))
     if name.startswith("i8emu") and name[5:].isdigit() and 1 <= int(name[5:]) <= 8:
         return (4, int(name[5:]))
     raise ValueError("unknown precision mode " + name)
@@ -117,12 +129,12 @@ def mode_flops(p, mode):
     """(binary64-equivalent flops, flops the matrix cores execute) per launch."""
     f = p.flops
     code, s = mode
-    return f, (f * s * (s + 1) / 2 if code in (3, 4) else f)
+    return f, (f * s * (s + 1) / 2 if code in (3, 4, 5) else f)
 
 
 def mode_peak(mode):
     return {0: PEAK_FP64, 1: PEAK_FP32_MFMA, 2: PEAK_BF16_MFMA, 3: PEAK_BF16_MFMA,
-            4: PEAK_INT8_MFMA}[mode[0]]
+            4: PEAK_INT8_MFMA, 5: PEAK_FP32_MFMA}[mode[0]]
 
 
 def precision_bench(args, h, parts):
@@ -159,8 +171,8 @@ def precision_bench(args, h, parts):
             fro.append(P.relative_errors(G, d2)[0])
             fro64.append(P.relative_errors(G, f64)[0])
             comp.append(float(np.max(np.abs(G - d2) / np.where(mag > 0, mag, 1.0))))
-            if mode[0] in (3, 4) and j == 0:
-                emu = P.emulated_gemm if mode[0] == 3 else P.int8_emulated_gemm
+            if mode[0] in (3, 4, 5) and j == 0:
+                emu = P.int8_emulated_gemm if mode[0] == 4 else P.emulated_gemm
                 ref = emu(Am, Bm, mode[1])
                 exact = bool(np.array_equal(G.view(np.int64), ref.view(np.int64)))
         for _ in range(args.warmup):
@@ -205,7 +217,8 @@ def precision_bench(args, h, parts):
         log("timing the CPU oracle of mode %s on a sample" % best["mode"])
         cpu = precision_cpu_baseline(p, bmode, args.cpu_seconds)
     dtype = {0: "f64", 1: "f32", 2: "bf16", 3: "bf16 slices (f32 sums, f64 recombination)",
-             4: "int8 slices (int32 sums, f64 recombination)"}[bmode[0]]
+             4: "int8 slices (int32 sums, f64 recombination)",
+             5: "8-bit digit slices on f32 matrix cores (f32 sums, f64 recombination)"}[bmode[0]]
     out = {"metric": METRIC, "value": best["gflops_fp64_equiv"], "unit": "GFLOP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
@@ -241,7 +254,7 @@ def precision_cpu_baseline(p, mode, seconds):
         else:
             Am, Bm = np.ascontiguousarray(A[:, :p.m].T), np.ascontiguousarray(B[:, :p.k].T)
             t0 = time.perf_counter()
-            if mode[0] == 3:
+            if mode[0] in (3, 5):
                 P.emulated_gemm(Am, Bm, mode[1])
             elif mode[0] == 4:
                 P.int8_emulated_gemm(Am, Bm, mode[1])
@@ -272,22 +285,34 @@ def serving_bench(args, h):
         # warm-up: one short schedule
         a, c, l = serve.requests(seed + 100, clients, 2000.0, 0.05)
         srv.run(a, c, l)
+        lockstep_rows = []
         for rate in [float(x) for x in args.rates.split(",")]:
-            srv.reset()
             a, c, l = serve.requests(seed, clients, rate, args.duration)
-            st, fi, ticks = srv.run(a, c, l)
-            n = sizes[c].astype(np.float64)
-            flops = float((2.0 * n ** 3 * l).sum())
-            wall = float(fi.max())
-            lat = (fi - a) * 1e3
-            row = {"offered_req_s": rate, "requests": int(len(a)),
-                   "achieved_req_s": round(len(a) / wall, 1), "gflops": round(flops / wall / 1e9, 1),
-                   "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                   "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                   "ticks": int(ticks), "mean_batch": round(float(l.sum()) / max(ticks, 1), 2),
-                   "wall_s": round(wall, 3)}
-            log(json.dumps(row))
-            rows.append(row)
+            # the same arrivals under continuous batching (the paper's tasked
+            # approach) and in lock-step rounds (its batched approach)
+            for policy, out_rows in ((serve.POLICY_CONTINUOUS, rows),
+                                     (serve.POLICY_LOCKSTEP, lockstep_rows)):
+                srv.reset()
+                srv.set_policy(policy)
+                st, fi, ticks = srv.run(a, c, l)
+                pool, peak, waits = srv.memory_stats()
+                n = sizes[c].astype(np.float64)
+                flops = float((2.0 * n ** 3 * l).sum())
+                wall = float(fi.max())
+                lat = (fi - a) * 1e3
+                row = {"offered_req_s": rate, "requests": int(len(a)),
+                       "achieved_req_s": round(len(a) / wall, 1),
+                       "gflops": round(flops / wall / 1e9, 1),
+                       "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                       "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                       "mean_ms": round(float(lat.mean()), 3),
+                       "ticks": int(ticks), "mean_batch": round(float(l.sum()) / max(ticks, 1), 2),
+                       "wall_s": round(wall, 3), "factor_pool_peak_bytes": int(peak),
+                       "memory_waits": int(waits)}
+                log(("continuous " if policy == serve.POLICY_CONTINUOUS else "lock step ") +
+                    json.dumps(row))
+                out_rows.append(row)
+            srv.set_policy(serve.POLICY_CONTINUOUS)
         # baseline: the same loop serving one request at a time (no batching
         # across clients), on a 0.1 s slice of the highest offered rate
         srv.reset()
@@ -373,7 +398,14 @@ def serving_bench(args, h):
            "config": {"workload": "config5", "clients": clients,
                       "state_sizes": sorted(set(int(x) for x in sizes)),
                       "duration_s": args.duration},
-           "roofline": roof, "cpu_baseline": cpu, "rates": rows, "one_at_a_time": serial,
+           "roofline": roof, "cpu_baseline": cpu, "rates": rows,
+           "lockstep_rates": lockstep_rows,
+           "continuous_vs_lockstep": {
+               "throughput_at_top_rate": round(top["achieved_req_s"] /
+                                               lockstep_rows[-1]["achieved_req_s"], 3),
+               "mean_latency_ratio_per_rate": [round(r["mean_ms"] / q["mean_ms"], 3)
+                                               for r, q in zip(rows, lockstep_rows)]},
+           "hbm_budget_bytes": 64 << 30, "one_at_a_time": serial,
            "sweeps_100x16": sw, "sweeps_100x16_32x32_states": sws,
            "batching_gain": round(top["achieved_req_s"] / serial["achieved_req_s"], 2),
            "parity_rel_fro_one_client": parity}
@@ -647,6 +679,27 @@ def cpu_baseline(parts, seconds):
                 100 * frac, ", ".join(desc), t)}
 
 
+def cold_part_ms(h, parts, reps, flush_bytes=1 << 30):
+    """Per-part event-timed milliseconds with the caches cold: before each
+    repetition a 1 GiB buffer (four times the 256 MB last-level cache) is
+    overwritten, then each part is launched once."""
+    import torch
+    flush = torch.empty(flush_bytes // 8, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in parts] for _ in range(reps)]
+    for r in range(reps):
+        for j, p in enumerate(parts):
+            flush.fill_(float(r + j))
+            ev[r][j][0].record(stream)
+            part_launch(h, p)
+            ev[r][j][1].record(stream)
+    torch.cuda.synchronize()
+    del flush
+    return [sum(ev[r][j][0].elapsed_time(ev[r][j][1]) for r in range(reps)) / reps
+            for j in range(len(parts))]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -656,7 +709,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=3, help="sampled parity instances per part")
-    ap.add_argument("--modes", default="fp64,fp32,bf16,emu3,emu6,emu7,i8emu6,i8emu7,i8emu8",
+    ap.add_argument("--cold", action="store_true",
+                    help="also time every part with cold caches (default for config1)")
+    ap.add_argument("--modes", default="fp64,fp32,bf16,emu3,emu6,emu7,f32emu3,f32emu6,i8emu6,i8emu7,"
+                                        "i8emu8",
                     help="precision modes timed by --workload config4")
     ap.add_argument("--rates", default="1000,5000,20000,50000",
                     help="offered request rates (per second) for --workload config5")
@@ -741,6 +797,16 @@ def main():
                           "bound": "mfma" if ai >= PEAK_FP64 / PEAK_HBM else "hbm",
                           "roofline_frac": round(t_roof / sec, 4),
                           "parity_max_rel_fro": parity.get(p.name)})
+    if args.cold or args.workload in ("config1", "u32"):
+        log("timing with cold caches")
+        for row, p, ms in zip(part_rows, parts, cold_part_ms(h, parts, max(3, args.steps))):
+            row["ms_cold"] = round(ms, 4)
+            if hasattr(p, "per_instance_roofline_s"):
+                t_roof = p.per_instance_roofline_s(PEAK_FP64, PEAK_HBM)
+            else:
+                t_roof = max(p.flops / PEAK_FP64, p.bytes / PEAK_HBM)
+            row["roofline_frac_cold"] = round(t_roof / (ms * 1e-3), 4)
+            row["gbps_cold"] = round(p.bytes / (ms * 1e-3) / 1e9, 1)
     dom = max(range(len(parts)), key=lambda j: part_rows[j]["ms"])
     dp, dr = parts[dom], part_rows[dom]
     sec = dr["ms"] * 1e-3

@@ -165,6 +165,11 @@ bg_status_t bg_dgemm_vbatched(bg_handle_t h, char transa, char transb,
  *                 f_j the exponents of row i's and column j's largest
  *                 magnitudes); 7 slices stay within 1e-14 relative on data
  *                 spread over 2^+-20, 8 match the binary64 path.
+ *   BG_MODE_EMU_F32 the digits, diagonals and recombination of BG_MODE_EMU
+ *                 with the digit products summed on the binary32 matrix
+ *                 cores (digits converted exactly to binary32; every partial
+ *                 sum is an integer below 2^24), so its results are
+ *                 bit-identical to BG_MODE_EMU with the same `slices`.
  * The paper computes in binary64 only (Section II); these modes are an
  * extension for callers that trade accuracy for matrix-core throughput. */
 typedef enum {
@@ -172,7 +177,8 @@ typedef enum {
   BG_MODE_FP32 = 1,
   BG_MODE_BF16 = 2,
   BG_MODE_EMU = 3,
-  BG_MODE_EMU_I8 = 4
+  BG_MODE_EMU_I8 = 4,
+  BG_MODE_EMU_F32 = 5
 } bg_mode_t;
 
 /* Uniform batch as bg_dgemm_batched, computed in `mode`.  Arguments, layout,
@@ -181,7 +187,8 @@ typedef enum {
  * every mode).  The reduced modes take non-transposed operands only
  * (transa == transb == 'N'); a transposed operand with such a mode returns
  * BG_STATUS_NOT_SUPPORTED.  A bad mode records argument number 101, a slice
- * count outside 1..8 for BG_MODE_EMU or BG_MODE_EMU_I8 records 102 (both
+ * count outside 1..8 for BG_MODE_EMU, BG_MODE_EMU_I8 or BG_MODE_EMU_F32
+ * records 102 (both
  * INVALID_VALUE). */
 bg_status_t bg_gemm_batched_mode(bg_handle_t h, int mode, int slices, char transa, char transb,
                                  int m, int n, int k, double alpha,

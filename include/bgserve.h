@@ -21,18 +21,37 @@
  * of order one along long chains).
  *
  * Scheduling.  The server advances in ticks.  At each tick it admits the
- * requests whose arrival time has passed into per-client queues, starts the
- * oldest queued request of every idle client, and performs one product for
- * every client with an active request: one launch generating all of the
- * tick's factors, then one bg_dgemm_batched launch per distinct size.  A
- * request finishes at the end of the tick of its L-th product.  Results do
- * not depend on timing: each client's state is the product of its own factors
- * in order, computed with the library's fixed per-size reduction order.
+ * requests whose arrival time has passed into per-client queues, starts
+ * queued requests of idle clients (oldest first, as the policy, the active
+ * limit and the factor memory allow), and performs one product for every
+ * client with an active request: one launch generating all of the tick's
+ * factors, then one bg_dgemm_batched launch per distinct size.  A request
+ * finishes at the end of the tick of its L-th product.  Two policies:
+ *   BS_POLICY_CONTINUOUS  (default) a request starts as soon as its client is
+ *                         idle and memory allows: requests that arrive while
+ *                         others run join the next tick (continuous
+ *                         batching, the paper's tasked approach);
+ *   BS_POLICY_LOCKSTEP    requests start only when no request is active, so
+ *                         a round of requests runs in lock step until its
+ *                         longest chain ends before the next round forms (the
+ *                         paper's batched approach, Section III).
+ * Results do not depend on timing or policy: each client's state is the
+ * product of its own factors in order, computed with the library's fixed
+ * per-size reduction order.
  *
- * Memory.  bs_create allocates, on the handle's device, three n_c x n_c
- * buffers per client (two states, one factor) and small pointer / job arrays;
- * it refuses (BG_STATUS_ALLOC_FAILED) when their total exceeds the given HBM
- * budget.  Nothing is allocated while serving.
+ * Memory.  bs_create allocates, on the handle's device, two n_c x n_c state
+ * buffers per client (resident for the server's life), small pointer / job
+ * arrays, and one factor pool.  A request holds an n_c x n_c factor of the
+ * pool (256-byte aligned) from its start until its last product has
+ * completed; a request that does not fit waits in its queue until running
+ * requests release memory (the oldest waiting request is never overtaken).
+ * With a budget, the pool is the budget minus the resident part, capped at
+ * every client's factor at once; bs_create refuses (BG_STATUS_ALLOC_FAILED)
+ * a budget that cannot hold the resident part plus the largest factor.  A
+ * pool that holds every client's factor gives each client a fixed slot (no
+ * request ever waits for memory); a smaller one is handed out first-fit, so
+ * fragmentation can hold a request back beyond what the free total suggests.
+ * Nothing is allocated while serving.
  *
  * Threads.  A server is driven by one host thread at a time.
  */
@@ -55,7 +74,8 @@ bg_status_t bs_create(bg_handle_t h, int num_clients, const int* sizes, unsigned
                       unsigned long long budget, bs_server_t* out);
 bg_status_t bs_destroy(bs_server_t s);
 
-/* Device bytes the server of these sizes holds (the budget test). */
+/* Device bytes a server of these sizes holds with no budget: states, arrays
+ * and a factor pool holding every client's factor at once. */
 unsigned long long bs_bytes_needed(int num_clients, const int* sizes);
 
 /* States back to the identity, product counters to zero (synchronous). */
@@ -93,9 +113,22 @@ bg_status_t bs_fill_factor(unsigned long long seed, int c, long long j, int n, d
  * be captured); otherwise the same launches are issued one by one.  The results are identical either way.
  * out_seconds (may be NULL) receives the device time of the sweeps.  The
  * call allocates and frees its own small arrays and graphs (outside the
- * timed part); it is synchronous. */
+ * timed part); it is synchronous.  Every client holds a factor of the pool
+ * during the sweeps: ALLOC_FAILED when the pool cannot hold them all. */
 bg_status_t bs_run_sweeps(bs_server_t s, int sweeps, int chain, int use_graph,
                           double* out_seconds);
+
+#define BS_POLICY_CONTINUOUS 0
+#define BS_POLICY_LOCKSTEP 1
+/* Selects the start policy of later bs_run_schedule calls (see Scheduling). */
+bg_status_t bs_set_policy(bs_server_t s, int policy);
+
+/* Factor-pool figures: its size, the most of it in use at once since the
+ * last bs_run_schedule or bs_run_sweeps began, and the number of ticks of
+ * the last bs_run_schedule at which the oldest startable request waited for
+ * memory.  Any pointer may be NULL. */
+bg_status_t bs_memory_stats(bs_server_t s, unsigned long long* pool_bytes,
+                            unsigned long long* peak_bytes, long long* waits);
 
 /* Limits the number of requests active at once (0, the default: no limit,
  * every client with queued work is served at every tick).  With a limit,
@@ -105,12 +138,17 @@ bg_status_t bs_run_sweeps(bs_server_t s, int sweeps, int chain, int use_graph,
 bg_status_t bs_set_max_active(bs_server_t s, int max_active);
 
 /* Host-only replay of the scheduler on a virtual clock where every tick
- * lasts tick_s seconds, with the given max_active: fills out_start /
- * out_finish as bs_run_schedule would (tick start and end times), and
- * out_ticks.  Touches no device. */
-bg_status_t bs_simulate(int num_clients, int n_requests, const double* arrival_s,
+ * lasts tick_s seconds, with the given policy and max_active and, when
+ * pool_bytes > 0, a factor pool of that many bytes for clients of the given
+ * sizes (host array; may be NULL when pool_bytes == 0): fills out_start /
+ * out_finish as bs_run_schedule would (tick start and end times), out_ticks
+ * and out_mem_waits (either may be NULL).  Touches no device.
+ * ALLOC_FAILED when one client's factor exceeds the pool. */
+bg_status_t bs_simulate(int num_clients, const int* sizes, unsigned long long pool_bytes,
+                        int policy, int n_requests, const double* arrival_s,
                         const int* client, const int* length, double tick_s, int max_active,
-                        double* out_start, double* out_finish, long long* out_ticks);
+                        double* out_start, double* out_finish, long long* out_ticks,
+                        long long* out_mem_waits);
 
 #ifdef __cplusplus
 }

@@ -31,9 +31,9 @@ EXPORTS = ["bg_version", "bg_status_string", "bg_create", "bg_destroy", "bg_set_
            "bg_zgemm_batched", "bg_zgate2_batched"]
 
 # bg_mode_t
-MODE_FP64, MODE_FP32, MODE_BF16, MODE_EMU, MODE_EMU_I8 = 0, 1, 2, 3, 4
+MODE_FP64, MODE_FP32, MODE_BF16, MODE_EMU, MODE_EMU_I8, MODE_EMU_F32 = 0, 1, 2, 3, 4, 5
 MODES = {"fp64": MODE_FP64, "fp32": MODE_FP32, "bf16": MODE_BF16, "emu": MODE_EMU,
-         "i8emu": MODE_EMU_I8}
+         "i8emu": MODE_EMU_I8, "f32emu": MODE_EMU_F32}
 
 
 class BgemmError(RuntimeError):
@@ -248,7 +248,7 @@ class Handle:
     def batched_mode(self, mode, A, B, C, m, n, k, alpha=1.0, beta=0.0, slices=0, transa="N",
                      transb="N", ptrs=None):
         """As ``batched`` in precision mode ``mode`` ("fp64", "fp32", "bf16",
-        "emu", "i8emu" or a bg_mode_t value); ``slices`` is an emulated
+        "emu", "i8emu", "f32emu" or a bg_mode_t value); ``slices`` is an emulated
         mode's digit slice count (1..8)."""
         mode = MODES.get(mode, mode) if isinstance(mode, str) else mode
         if isinstance(mode, str):

@@ -18,6 +18,10 @@
 //          V = T 2^(e_i + f_j), acc += V over chunks in ascending order.
 //          Every rounding is fixed in kind and order, so the result is
 //          reproducible bit for bit by a CPU implementation of these steps.
+//   emu32: the same digits and sums on the binary32 matrix cores
+//          (v_mfma_f32_16x16x4_f32, digits converted exactly to binary32):
+//          every digit product and every partial sum is an integer below
+//          2^24, so the sums, and the whole result, are bit-identical to emu.
 //
 // Tile: 64 x 64 of C per workgroup (four waves of 32 x 32, i.e. 2 x 2 blocks
 // of 16 x 16), one 32-wide chunk of k per step.  Each step stages the binary64
@@ -48,7 +52,12 @@ constexpr int S64B = BKC + 1;   // staging B: [n][k], doubles
 constexpr int SF = BKC + 4;     // fp32 operand rows (floats): bank-distinct 4-byte reads
 constexpr int SH = BKC + 8;     // bf16 operand rows (halves): 80-byte stride, distinct 16-byte reads
 
-enum Mode { FP32 = 1, BF16 = 2, EMU = 3 };
+enum Mode { FP32 = 1, BF16 = 2, EMU = 3, EMU32 = 5 };
+
+// a digit held as bfloat16 bits, as the binary32 value it represents (exact)
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float((unsigned int)h << 16);
+}
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned int u = __float_as_uint(f);
@@ -61,9 +70,12 @@ __device__ __forceinline__ unsigned short bf16_exact(float f) {
   return (unsigned short)(__float_as_uint(f) >> 16);
 }
 
+// the digit-slice modes
+constexpr bool is_emu(int mode) { return mode == EMU || mode == EMU32; }
+
 template <int MODE, int S>
 struct __align__(16) Smem {
-  static constexpr int NSL = MODE == EMU ? S : 1;
+  static constexpr int NSL = is_emu(MODE) ? S : 1;
   double a64[BKC * S64A];
   double b64[BN * S64B];
   int ea[BM], fb[BN];
@@ -84,7 +96,7 @@ __global__ __launch_bounds__(NT) void k_lowp(int M, int N, int K, double alpha,
   // which is what makes the emulated mode reproducible bit for bit
 #pragma clang fp contract(off)
   __shared__ Smem<MODE, S> sm;
-  constexpr int NG = MODE == EMU ? S : 1;   // accumulator sets (diagonals g = 2..S+1)
+  constexpr int NG = is_emu(MODE) ? S : 1;   // accumulator sets (diagonals g = 2..S+1)
   const int64_t bid = blockIdx.x;
   const int64_t id = (bid % 8) * per_xcd + bid / 8;   // contiguous tiles per XCD
   if (id >= total_tiles) return;
@@ -133,7 +145,7 @@ __global__ __launch_bounds__(NT) void k_lowp(int M, int N, int K, double alpha,
     }
     __syncthreads();
     // 2. (emu) chunk exponents of the 64 rows of A and 64 columns of B
-    if constexpr (MODE == EMU) {
+    if constexpr (is_emu(MODE)) {
       if (tid < BM) {
         double mx = 0.0;
         for (int kk = 0; kk < BKC; ++kk) mx = fmax(mx, fabs(sm.a64[kk * S64A + tid]));
@@ -216,6 +228,32 @@ __global__ __launch_bounds__(NT) void k_lowp(int M, int N, int K, double alpha,
           for (int bj = 0; bj < 2; ++bj)
             acc32[0][bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(fbv[bj], fa[bi], acc32[0][bi][bj], 0, 0, 0);
       }
+    } else if constexpr (MODE == EMU32) {
+      // per diagonal pair (t, u): eight 4-wide steps of k on the binary32
+      // matrix cores; lane (li, lg) takes digit k = ks + lg of row / column li
+#pragma unroll
+      for (int t = 1; t <= S; ++t) {
+#pragma unroll
+        for (int u = 1; u <= S; ++u) {
+          if (t + u > S + 1) continue;
+          const int g = t + u - 2;
+#pragma unroll
+          for (int ks = 0; ks < BKC; ks += 4) {
+            float fa[2], fbv[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              fa[b] = bf16_to_f32(sm.op.h16.a[t - 1][(wm0 + 16 * b + li) * SH + ks + lg]);
+              fbv[b] = bf16_to_f32(sm.op.h16.b[u - 1][(wn0 + 16 * b + li) * SH + ks + lg]);
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+              for (int bj = 0; bj < 2; ++bj)
+                acc32[g][bi][bj] =
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(fbv[bj], fa[bi], acc32[g][bi][bj], 0, 0, 0);
+          }
+        }
+      }
     } else {
 #pragma unroll
       for (int t = 1; t <= (MODE == EMU ? S : 1); ++t) {
@@ -238,8 +276,10 @@ __global__ __launch_bounds__(NT) void k_lowp(int M, int N, int K, double alpha,
               acc32[g][bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vb[bj], va[bi], acc32[g][bi][bj], 0, 0, 0);
         }
       }
+    }
+    if constexpr (MODE != FP32) {
       // 5. (emu) fold this chunk into binary64 in the fixed order
-      if constexpr (MODE == EMU) {
+      if constexpr (is_emu(MODE)) {
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -291,7 +331,7 @@ __global__ __launch_bounds__(NT) void k_lowp(int M, int N, int K, double alpha,
           if (beta == 1.0) continue;
           x = beta == 0.0 ? 0.0 : beta * cv[bi][bj][v];
         } else {
-          const double p = MODE == EMU ? acc64[bi][bj][v] : (double)acc32[0][bi][bj][v];
+          const double p = is_emu(MODE) ? acc64[bi][bj][v] : (double)acc32[0][bi][bj][v];
           x = alpha * p;
           if (beta != 0.0) x = x + beta * cv[bi][bj][v];
         }
@@ -318,6 +358,19 @@ hipError_t launch_uniform_lowp(const UniformArgs& a, int mode, int slices, hipSt
   using namespace lowp;
   if (mode == FP32) return launch<FP32, 1>(a, s);
   if (mode == BF16) return launch<BF16, 1>(a, s);
+  if (mode == EMU32) {
+    switch (slices) {
+      case 1: return launch<EMU32, 1>(a, s);
+      case 2: return launch<EMU32, 2>(a, s);
+      case 3: return launch<EMU32, 3>(a, s);
+      case 4: return launch<EMU32, 4>(a, s);
+      case 5: return launch<EMU32, 5>(a, s);
+      case 6: return launch<EMU32, 6>(a, s);
+      case 7: return launch<EMU32, 7>(a, s);
+      case 8: return launch<EMU32, 8>(a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (slices) {
     case 1: return launch<EMU, 1>(a, s);
     case 2: return launch<EMU, 2>(a, s);

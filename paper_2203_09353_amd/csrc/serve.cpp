@@ -7,6 +7,7 @@
 #include <cmath>
 #include <deque>
 #include <limits>
+#include <map>
 #include <thread>
 #include <vector>
 
@@ -17,9 +18,81 @@
 
 namespace bs {
 
+// Factor memory of one device region [0, bytes): host bookkeeping of offsets
+// only (the region itself is allocated once, at bs_create).  A client has at
+// most one active request, so when the region holds every client's factor at
+// once each client gets a fixed slot; otherwise requests take first-fit
+// ranges, adjacent free ranges merged on release.
+struct Pool {
+  static constexpr size_t kAlign = 256;
+  static constexpr size_t npos = (size_t)-1;
+  std::map<size_t, size_t> free_;   // offset -> length (first-fit mode)
+  std::vector<size_t> fixed;        // per-client slot (fixed mode), else empty
+  size_t bytes = 0, used = 0, peak = 0;
+  static size_t round(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+  void init(size_t b, const size_t* need, int nc) {
+    free_.clear();
+    fixed.clear();
+    bytes = b;
+    used = peak = 0;
+    size_t all = 0;
+    for (int c = 0; c < nc; ++c) all += round(need[c]);
+    if (all <= b) {
+      fixed.resize(nc);
+      size_t off = 0;
+      for (int c = 0; c < nc; ++c) {
+        fixed[c] = off;
+        off += round(need[c]);
+      }
+    } else if (b) {
+      free_[0] = b;
+    }
+  }
+  size_t alloc(int c, size_t b) {
+    b = round(b);
+    if (!fixed.empty()) {
+      used += b;
+      peak = std::max(peak, used);
+      return fixed[c];
+    }
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < b) continue;
+      const size_t off = it->first, rest = it->second - b;
+      free_.erase(it);
+      if (rest) free_[off + b] = rest;
+      used += b;
+      peak = std::max(peak, used);
+      return off;
+    }
+    return npos;
+  }
+  void release(size_t off, size_t b) {
+    b = round(b);
+    used -= b;
+    if (!fixed.empty()) return;
+    auto it = free_.emplace(off, b).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
 // Per-client FIFO queues and the one active request of each client.  Pure
 // host logic, shared by the device loop and the virtual-clock replay.
 struct Scheduler {
+  struct Done {
+    int r, c;
+    size_t off;
+  };
   int nc = 0, nreq = 0;
   const double* arrival = nullptr;
   const int* client = nullptr;
@@ -28,8 +101,23 @@ struct Scheduler {
   double* finish = nullptr;
   std::vector<std::deque<int>> queue;
   std::vector<int> active, remaining;
-  std::vector<int> batch;   // clients served by the current tick, ascending
+  std::vector<size_t> slot;  // offset of each active request's factor in the pool
+  std::vector<int> batch;    // clients served by the current tick, ascending
+  std::vector<int> cand;
   int next = 0, finished = 0;
+  // policy 0 (continuous batching): requests start whenever their client is
+  // idle; policy 1 (lock step): requests start only when no request is
+  // active, so each round of requests runs to its longest chain before the
+  // next round forms -- the lock-step batch of the paper's batched approach.
+  int policy = 0;
+  int max_active = 0;
+  int n_active = 0;
+  // Factor memory: with a pool, a request holds need[c] bytes of it from its
+  // start until its last product has completed; a request that does not fit
+  // waits (requests start oldest first, so none overtakes it).
+  Pool* pool = nullptr;
+  const size_t* need = nullptr;
+  long long mem_waits = 0;   // ticks at which the oldest startable request waited for memory
 
   void init(int num_clients, int n, const double* arr, const int* cl, const int* len, double* st,
             double* fin) {
@@ -37,23 +125,23 @@ struct Scheduler {
     queue.assign(nc, {});
     active.assign(nc, -1);
     remaining.assign(nc, 0);
+    slot.assign(nc, 0);
     batch.clear();
     next = finished = 0;
     n_active = 0;
+    mem_waits = 0;
   }
   void admit(double now) {
     while (next < nreq && arrival[next] <= now) queue[client[next]].push_back(next++);
   }
-  // Starts queued requests of idle clients -- with no limit (max_active 0)
-  // the oldest queued request of every idle client, otherwise the oldest
-  // startable requests while fewer than max_active are active -- then the
-  // tick serves every client with an active request.  A request whose last
+  // Starts queued requests of idle clients, oldest first, while the policy,
+  // max_active (0: no limit) and the factor memory allow; then the tick
+  // serves every client with an active request.  A request whose last
   // product is in this tick is listed in `last` and leaves its client idle
   // for the next tick (whose product on the same state is ordered after this
-  // one on the device); it counts as finished when the tick completes.
-  std::vector<int> last;
-  int max_active = 0;
-  int n_active = 0;
+  // one on the device); it counts as finished, and its memory is released,
+  // when the tick completes.
+  std::vector<Done> last;
   void start_request(int c, double now) {
     const int r = queue[c].front();
     queue[c].pop_front();
@@ -65,25 +153,31 @@ struct Scheduler {
   int begin_tick(double now) {
     batch.clear();
     last.clear();
-    if (max_active <= 0) {
+    if (!(policy == 1 && n_active > 0)) {
+      cand.clear();
       for (int c = 0; c < nc; ++c)
-        if (active[c] < 0 && !queue[c].empty()) start_request(c, now);
-    } else {
-      while (n_active < max_active) {
-        int best = -1;
-        for (int c = 0; c < nc; ++c)
-          if (active[c] < 0 && !queue[c].empty() &&
-              (best < 0 || queue[c].front() < queue[best].front()))
-            best = c;
-        if (best < 0) break;
-        start_request(best, now);
+        if (active[c] < 0 && !queue[c].empty()) cand.push_back(c);
+      std::sort(cand.begin(), cand.end(),
+                [&](int a, int b) { return queue[a].front() < queue[b].front(); });
+      for (int c : cand) {
+        if (max_active > 0 && n_active >= max_active) break;
+        size_t off = 0;
+        if (pool) {
+          off = pool->alloc(c, need[c]);
+          if (off == Pool::npos) {
+            ++mem_waits;
+            break;
+          }
+        }
+        slot[c] = off;
+        start_request(c, now);
       }
     }
     for (int c = 0; c < nc; ++c) {
       if (active[c] >= 0) {
         batch.push_back(c);
         if (--remaining[c] == 0) {
-          last.push_back(active[c]);
+          last.push_back(Done{active[c], c, slot[c]});
           active[c] = -1;
           --n_active;
         }
@@ -91,8 +185,11 @@ struct Scheduler {
     }
     return (int)batch.size();
   }
-  void complete(const std::vector<int>& fin, double now) {
-    for (int r : fin) finish[r] = now;
+  void complete(const std::vector<Done>& fin, double now) {
+    for (const Done& d : fin) {
+      finish[d.r] = now;
+      if (pool) pool->release(d.off, need[d.c]);
+    }
     finished += (int)fin.size();
   }
   bool done() const { return finished == nreq; }
@@ -121,7 +218,11 @@ struct bs_server {
   std::vector<int> sizes;
   std::vector<double> scale;
   std::vector<double*> st[2];
-  std::vector<double*> fac;
+  // factor memory: one device region, handed out per active request
+  char* pool_base;
+  size_t pool_bytes;
+  bs::Pool pool;
+  std::vector<size_t> need;       // factor bytes of each client
   std::vector<int> cur;
   std::vector<long long> products;
   // two sets of job / pointer arrays, so one tick can be prepared while the
@@ -133,17 +234,21 @@ struct bs_server {
   hipEvent_t ev[2];
   hipEvent_t ev0;
   int max_active;
+  int policy;
+  long long mem_waits;            // of the last bs_run_schedule
 };
 
 static const unsigned kServerMagic = 0x5E7BE5E7u;
 static bool valid(bs_server_t s) { return s && s->magic == kServerMagic; }
 
-static size_t client_bytes(int n) { return 3 * (size_t)n * (size_t)n * sizeof(double); }
+static size_t state_bytes(int n) { return 2 * (size_t)n * (size_t)n * sizeof(double); }
+static size_t factor_bytes(int n) { return bs::Pool::round((size_t)n * (size_t)n * sizeof(double)); }
+static size_t array_bytes(int nc) { return 2ull * nc * (sizeof(bg::FillJob) + 3 * sizeof(double*)); }
 
 static void free_all(bs_server* s) {
   for (int b = 0; b < 2; ++b)
     for (double* p : s->st[b]) if (p) (void)hipFree(p);
-  for (double* p : s->fac) if (p) (void)hipFree(p);
+  if (s->pool_base) (void)hipFree(s->pool_base);
   for (int b = 0; b < 2; ++b) {
     if (s->d_jobs[b]) (void)hipFree(s->d_jobs[b]);
     if (s->d_ptrs[b]) (void)hipFree((void*)s->d_ptrs[b]);
@@ -168,9 +273,8 @@ unsigned long long bs_bytes_needed(int num_clients, const int* sizes) {
   if (num_clients <= 0 || !sizes) return 0;
   unsigned long long t = 0;
   for (int c = 0; c < num_clients; ++c)
-    if (sizes[c] > 0) t += client_bytes(sizes[c]);
-  t += 2ull * num_clients * (sizeof(bg::FillJob) + 3 * sizeof(double*));
-  return t;
+    if (sizes[c] > 0) t += state_bytes(sizes[c]) + factor_bytes(sizes[c]);
+  return t + array_bytes(num_clients);
 }
 
 bg_status_t bs_create(bg_handle_t h, int num_clients, const int* sizes, unsigned long long seed,
@@ -178,7 +282,20 @@ bg_status_t bs_create(bg_handle_t h, int num_clients, const int* sizes, unsigned
   if (!out || !h || num_clients <= 0 || num_clients > 65535 || !sizes) return BG_STATUS_INVALID_VALUE;
   for (int c = 0; c < num_clients; ++c)
     if (sizes[c] < 1 || sizes[c] > 4096) return BG_STATUS_INVALID_VALUE;
-  if (budget && bs_bytes_needed(num_clients, sizes) > budget) return BG_STATUS_ALLOC_FAILED;
+  // States and arrays stay resident; the rest of the budget is the factor
+  // pool, which must hold at least the largest client's factor and need not
+  // hold more than every client's at once.
+  size_t fixed = array_bytes(num_clients), all_factors = 0, largest = 0;
+  for (int c = 0; c < num_clients; ++c) {
+    fixed += state_bytes(sizes[c]);
+    all_factors += factor_bytes(sizes[c]);
+    largest = std::max(largest, factor_bytes(sizes[c]));
+  }
+  size_t pool_bytes = all_factors;
+  if (budget) {
+    if (fixed + largest > budget) return BG_STATUS_ALLOC_FAILED;
+    pool_bytes = std::min(all_factors, (size_t)budget - fixed);
+  }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return BG_STATUS_DEVICE_ERROR;
   bs_server* s = new bs_server();
@@ -191,16 +308,21 @@ bg_status_t bs_create(bg_handle_t h, int num_clients, const int* sizes, unsigned
   s->scale.resize(num_clients);
   s->st[0].assign(num_clients, nullptr);
   s->st[1].assign(num_clients, nullptr);
-  s->fac.assign(num_clients, nullptr);
+  s->pool_base = nullptr;
+  s->pool_bytes = pool_bytes;
+  s->need.resize(num_clients);
+  s->policy = 0;
+  s->mem_waits = 0;
   s->cur.assign(num_clients, 0);
   s->products.assign(num_clients, 0);
   bool ok = true;
   for (int c = 0; c < num_clients && ok; ++c) {
     const size_t b = (size_t)sizes[c] * sizes[c] * sizeof(double);
     s->scale[c] = std::sqrt(3.0 / (double)sizes[c]);
-    ok = hipMalloc(&s->st[0][c], b) == hipSuccess && hipMalloc(&s->st[1][c], b) == hipSuccess &&
-         hipMalloc(&s->fac[c], b) == hipSuccess;
+    s->need[c] = factor_bytes(sizes[c]);
+    ok = hipMalloc(&s->st[0][c], b) == hipSuccess && hipMalloc(&s->st[1][c], b) == hipSuccess;
   }
+  ok = ok && hipMalloc((void**)&s->pool_base, pool_bytes) == hipSuccess;
   for (int b = 0; b < 2 && ok; ++b)
     ok = hipMalloc(&s->d_jobs[b], num_clients * sizeof(bg::FillJob)) == hipSuccess &&
          hipMalloc((void**)&s->d_ptrs[b], 3 * num_clients * sizeof(double*)) == hipSuccess &&
@@ -274,16 +396,51 @@ bg_status_t bs_set_max_active(bs_server_t s, int max_active) {
   return BG_STATUS_SUCCESS;
 }
 
-bg_status_t bs_simulate(int num_clients, int n_requests, const double* arrival_s,
-                        const int* client, const int* length, double tick_s, int max_active,
-                        double* out_start, double* out_finish, long long* out_ticks) {
+bg_status_t bs_set_policy(bs_server_t s, int policy) {
+  if (!valid(s)) return BG_STATUS_INVALID_HANDLE;
+  if (policy != BS_POLICY_CONTINUOUS && policy != BS_POLICY_LOCKSTEP) return BG_STATUS_INVALID_VALUE;
+  s->policy = policy;
+  return BG_STATUS_SUCCESS;
+}
+
+bg_status_t bs_memory_stats(bs_server_t s, unsigned long long* pool_bytes,
+                            unsigned long long* peak_bytes, long long* waits) {
+  if (!valid(s)) return BG_STATUS_INVALID_HANDLE;
+  if (pool_bytes) *pool_bytes = s->pool_bytes;
+  if (peak_bytes) *peak_bytes = s->pool.peak;
+  if (waits) *waits = s->mem_waits;
+  return BG_STATUS_SUCCESS;
+}
+
+bg_status_t bs_simulate(int num_clients, const int* sizes, unsigned long long pool_bytes,
+                        int policy, int n_requests, const double* arrival_s, const int* client,
+                        const int* length, double tick_s, int max_active, double* out_start,
+                        double* out_finish, long long* out_ticks, long long* out_mem_waits) {
   if (num_clients <= 0 || !(tick_s > 0.0) || max_active < 0 ||
+      (policy != BS_POLICY_CONTINUOUS && policy != BS_POLICY_LOCKSTEP) ||
+      (pool_bytes && !sizes) ||
       !bs::valid_schedule(num_clients, n_requests, arrival_s, client, length) ||
       (n_requests > 0 && (!out_start || !out_finish)))
     return BG_STATUS_INVALID_VALUE;
+  std::vector<size_t> need;
+  bs::Pool pool;
+  if (pool_bytes) {
+    need.resize(num_clients);
+    for (int c = 0; c < num_clients; ++c) {
+      if (sizes[c] < 1 || sizes[c] > 4096) return BG_STATUS_INVALID_VALUE;
+      need[c] = factor_bytes(sizes[c]);
+      if (need[c] > pool_bytes) return BG_STATUS_ALLOC_FAILED;
+    }
+    pool.init((size_t)pool_bytes, need.data(), num_clients);
+  }
   bs::Scheduler sc;
   sc.init(num_clients, n_requests, arrival_s, client, length, out_start, out_finish);
   sc.max_active = max_active;
+  sc.policy = policy;
+  if (pool_bytes) {
+    sc.pool = &pool;
+    sc.need = need.data();
+  }
   double now = 0.0;
   long long ticks = 0;
   while (!sc.done()) {
@@ -297,6 +454,7 @@ bg_status_t bs_simulate(int num_clients, int n_requests, const double* arrival_s
     ++ticks;
   }
   if (out_ticks) *out_ticks = ticks;
+  if (out_mem_waits) *out_mem_waits = sc.mem_waits;
   return BG_STATUS_SUCCESS;
 }
 
@@ -313,13 +471,17 @@ bg_status_t bs_run_schedule(bs_server_t s, int n_requests, const double* arrival
   bs::Scheduler sc;
   sc.init(s->nc, n_requests, arrival_s, client, length, out_start, out_finish);
   sc.max_active = s->max_active;
+  sc.policy = s->policy;
+  s->pool.init(s->pool_bytes, s->need.data(), s->nc);
+  sc.pool = &s->pool;
+  sc.need = s->need.data();
   using clk = std::chrono::steady_clock;
   // Up to two ticks in flight: the host prepares and launches tick t + 1
   // while tick t runs.  A tick's completion time is read from its event
   // relative to an event recorded when the call starts.
   struct InFlight {
     int set;
-    std::vector<int> fin;
+    std::vector<bs::Scheduler::Done> fin;
   };
   std::deque<InFlight> flight;
   if (hipStreamSynchronize(stream) != hipSuccess || hipEventRecord(s->ev0, stream) != hipSuccess)
@@ -367,8 +529,9 @@ bg_status_t bs_run_schedule(bs_server_t s, int n_requests, const double* arrival
     const double** dp = s->d_ptrs[set];
     for (int i = 0; i < nb; ++i) {
       const int c = order[i];
-      hj[i] = bg::FillJob{s->fac[c], s->products[c], s->sizes[c], c, s->scale[c]};
-      hp[i] = s->fac[c];
+      double* f = (double*)(s->pool_base + sc.slot[c]);
+      hj[i] = bg::FillJob{f, s->products[c], s->sizes[c], c, s->scale[c]};
+      hp[i] = f;
       hp[nb + i] = s->st[s->cur[c]][c];
       hp[2 * nb + i] = s->st[s->cur[c] ^ 1][c];
     }
@@ -402,6 +565,7 @@ bg_status_t bs_run_schedule(bs_server_t s, int n_requests, const double* arrival
     ++ticks;
   }
   if (out_ticks) *out_ticks = ticks;
+  s->mem_waits = sc.mem_waits;
   return BG_STATUS_SUCCESS;
 }
 
@@ -419,12 +583,20 @@ bg_status_t bs_run_sweeps(bs_server_t s, int sweeps, int chain, int use_graph,
   for (int c = 0; c < nc; ++c) order[c] = c;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return s->sizes[a] < s->sizes[b]; });
+  // every client takes part in every sweep: each holds a factor of the pool
+  s->pool.init(s->pool_bytes, s->need.data(), nc);
+  std::vector<double*> fac(nc);
+  for (int c = 0; c < nc; ++c) {
+    const size_t off = s->pool.alloc(c, s->need[c]);
+    if (off == bs::Pool::npos) return BG_STATUS_ALLOC_FAILED;
+    fac[c] = (double*)(s->pool_base + off);
+  }
   int max_n = 0;
   std::vector<bg::SweepJob> jobs(nc);
   std::vector<long long> j0(nc);
   for (int i = 0; i < nc; ++i) {
     const int c = order[i];
-    jobs[i] = bg::SweepJob{s->fac[c], s->sizes[c], c, s->scale[c]};
+    jobs[i] = bg::SweepJob{fac[c], s->sizes[c], c, s->scale[c]};
     max_n = std::max(max_n, s->sizes[c]);
   }
   for (int c = 0; c < nc; ++c) j0[c] = s->products[c];
@@ -435,7 +607,7 @@ bg_status_t bs_run_sweeps(bs_server_t s, int sweeps, int chain, int use_graph,
       for (int i = 0; i < nc; ++i) {
         const int c = order[i];
         const int cur = s->cur[c] ^ p ^ (t & 1);
-        row[i] = s->fac[c];
+        row[i] = fac[c];
         row[nc + i] = s->st[cur][c];
         row[2 * nc + i] = s->st[cur ^ 1][c];
       }

@@ -43,7 +43,13 @@ def _lib():
         L.bs_fill_factor.restype = i
         L.bs_fill_factor.argtypes = [u64, i, ll, i, vp, vp]
         L.bs_simulate.restype = i
-        L.bs_simulate.argtypes = [i, i, vp, vp, vp, d, i, vp, vp, ctypes.POINTER(ll)]
+        L.bs_simulate.argtypes = [i, vp, u64, i, i, vp, vp, vp, d, i, vp, vp,
+                                  ctypes.POINTER(ll), ctypes.POINTER(ll)]
+        L.bs_set_policy.restype = i
+        L.bs_set_policy.argtypes = [vp, i]
+        L.bs_memory_stats.restype = i
+        L.bs_memory_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                      ctypes.POINTER(ll)]
         L.bs_run_sweeps.restype = i
         L.bs_run_sweeps.argtypes = [vp, i, i, i, ctypes.POINTER(d)]
         L.bs_set_max_active.restype = i
@@ -65,17 +71,26 @@ def bytes_needed(sizes) -> int:
     return int(_lib().bs_bytes_needed(len(s), _ptr(s)))
 
 
-def simulate(num_clients, arrivals, clients, lengths, tick_s, max_active=0):
+POLICY_CONTINUOUS, POLICY_LOCKSTEP = 0, 1
+
+
+def simulate(num_clients, arrivals, clients, lengths, tick_s, max_active=0,
+             policy=POLICY_CONTINUOUS, sizes=None, pool_bytes=0, with_waits=False):
     """Host-only replay of the scheduler on a virtual clock (no device):
-    returns (start, finish, ticks)."""
+    returns (start, finish, ticks), plus the memory waits if `with_waits`."""
     a, c, l = _arr(arrivals, np.float64), _arr(clients, np.int32), _arr(lengths, np.int32)
     n = len(a)
     st, fi = np.zeros(n), np.zeros(n)
-    ticks = ctypes.c_longlong()
-    r = _lib().bs_simulate(num_clients, n, _ptr(a), _ptr(c), _ptr(l), float(tick_s),
-                           int(max_active), _ptr(st), _ptr(fi), ctypes.byref(ticks))
+    ticks, waits = ctypes.c_longlong(), ctypes.c_longlong()
+    sz = None if sizes is None else _arr(sizes, np.int32)
+    r = _lib().bs_simulate(num_clients, None if sz is None else _ptr(sz), int(pool_bytes),
+                           int(policy), n, _ptr(a), _ptr(c), _ptr(l), float(tick_s),
+                           int(max_active), _ptr(st), _ptr(fi), ctypes.byref(ticks),
+                           ctypes.byref(waits))
     if r != 0:
         raise bgemm.BgemmError("bs_simulate", r)
+    if with_waits:
+        return st, fi, ticks.value, waits.value
     return st, fi, ticks.value
 
 
@@ -129,6 +144,20 @@ class Server:
         r = self.L.bs_set_max_active(self._s, int(k))
         if r != 0:
             raise bgemm.BgemmError("bs_set_max_active", r)
+
+    def set_policy(self, policy: int):
+        """POLICY_CONTINUOUS (default) or POLICY_LOCKSTEP."""
+        r = self.L.bs_set_policy(self._s, int(policy))
+        if r != 0:
+            raise bgemm.BgemmError("bs_set_policy", r)
+
+    def memory_stats(self):
+        """(pool bytes, peak bytes in use, ticks that waited for memory)."""
+        pb, pk, w = ctypes.c_ulonglong(), ctypes.c_ulonglong(), ctypes.c_longlong()
+        r = self.L.bs_memory_stats(self._s, ctypes.byref(pb), ctypes.byref(pk), ctypes.byref(w))
+        if r != 0:
+            raise bgemm.BgemmError("bs_memory_stats", r)
+        return pb.value, pk.value, w.value
 
     def reset(self):
         self.handle._sync_stream()

@@ -90,6 +90,24 @@ def test_emulated_bit_exact_wide_exponents(h, spread):
             assert np.array_equal(G.view(np.int64), ref.view(np.int64)), (spread, s)
 
 
+@pytest.mark.parametrize("s", [1, 3, 6, 8])
+def test_emulated_on_binary32_cores_bit_exact(h, s):
+    """BG_MODE_EMU_F32: the same digits summed on the binary32 matrix cores
+    give the oracle's bits (and so the bfloat16-core mode's), with tails in m,
+    n and k, padding, alpha / beta and a wide exponent spread."""
+    for m, n, k, alpha, beta, spread in ((70, 45, 100, 1.0, 0.0, 0), (65, 63, 33, -0.75, 1.5, 0),
+                                         (17, 3, 500, 2.0, -1.0, 20)):
+        res = run_mode(h, "f32emu", s, m, n, k, alpha, beta, pads=(3, 1, 2), seed=40 + s,
+                       spread=spread)
+        for G, Am, Bm, C0 in res:
+            ref = P.emulated_gemm(Am, Bm, s, alpha, beta, C0)
+            assert np.array_equal(G.view(np.int64), ref.view(np.int64)), (s, m, n, k)
+        res16 = run_mode(h, "emu", s, m, n, k, alpha, beta, pads=(3, 1, 2), seed=40 + s,
+                         spread=spread)
+        for (G, _, _, _), (G16, _, _, _) in zip(res, res16):
+            assert np.array_equal(G.view(np.int64), G16.view(np.int64))
+
+
 def test_emulated_zero_rows_and_columns(h):
     A, B, C = _operands(21, 40, 40, 64, 2, (0, 0, 0), 0)
     A[:, :32, 5] = 0.0        # row 5 of A zero in the first chunk

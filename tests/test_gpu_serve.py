@@ -78,9 +78,13 @@ def test_results_identical_alone_and_in_the_mix(h):
 
 def test_budget_and_argument_errors(h):
     need = serve.bytes_needed(SIZES)
+    factor = [(n * n * 8 + 255) // 256 * 256 for n in SIZES]
+    resident = need - sum(factor)
+    # the resident states plus the largest factor is the least budget
     with pytest.raises(bgemm.BgemmError) as e:
-        serve.Server(h, SIZES, seed=1, budget=need - 1)
+        serve.Server(h, SIZES, seed=1, budget=resident + max(factor) - 1)
     assert e.value.status == 4
+    serve.Server(h, SIZES, seed=1, budget=resident + max(factor)).close()
     with pytest.raises(bgemm.BgemmError) as e:
         serve.Server(h, [32, 0], seed=1)
     assert e.value.status == 1
@@ -158,3 +162,38 @@ def test_sweeps_argument_errors_and_zero_sweeps(h):
                 assert p == 0 and np.array_equal(S, np.eye(n))
     finally:
         srv.close()
+
+
+def test_lockstep_and_tight_memory_give_the_same_states(h):
+    """The lock-step policy and a budget that admits one large factor at a
+    time change only when products run, not what they compute: final states
+    are bit-identical to continuous batching with no memory limit."""
+    a, c, l = _schedule()
+    ref = serve.Server(h, SIZES, seed=31)
+    try:
+        ref.run(a, c, l)
+        want = {cl: ref.state(cl) for cl in range(len(SIZES))}
+        _, _, waits = ref.memory_stats()
+        assert waits == 0
+    finally:
+        ref.close()
+    need = serve.bytes_needed(SIZES)
+    factor = [(n * n * 8 + 255) // 256 * 256 for n in SIZES]
+    tight = need - sum(factor) + max(factor) + factor[0]
+    for policy, budget in ((serve.POLICY_LOCKSTEP, 0), (serve.POLICY_CONTINUOUS, tight),
+                           (serve.POLICY_LOCKSTEP, tight)):
+        srv = serve.Server(h, SIZES, seed=31, budget=budget)
+        try:
+            srv.set_policy(policy)
+            st, fi, ticks = srv.run(a, c, l)
+            assert np.all(st >= a) and np.all(fi > st)
+            pool, peak, waits = srv.memory_stats()
+            assert peak <= pool
+            if budget:
+                assert pool == max(factor) + factor[0] and waits > 0
+            for cl in range(len(SIZES)):
+                S, p = srv.state(cl)
+                W, pw = want[cl]
+                assert p == pw and np.array_equal(S.view(np.int64), W.view(np.int64)), (policy, cl)
+        finally:
+            srv.close()

@@ -164,3 +164,53 @@ def test_vbatched_errors(h):
     assert h.dgemm_vbatched_raw("N", "N", None, None, None, 1.0, None, None, None, None, 0.0,
                                 None, None, 3, None) == 1
     assert h.last_invalid_arg() == 3
+
+
+def test_vbatched_without_tile_map_and_workspace_too_small():
+    """A workspace of exactly bg_workspace_bytes_needed(batch) bytes leaves no
+    room for the tile -> instance map, so the executor finds each tile's
+    instance by binary search over the per-class prefix sums.  The results
+    must match the oracle and be bit-identical to the map path; one byte less
+    must be refused with BG_STATUS_WORKSPACE_TOO_SMALL and leave C untouched."""
+    batch = 700
+    ms, ns, ks = sizes(26, batch)
+    As, Bs, Cs, la, lb, lc, shp = make_batch(8, ms, ns, ks, "N", "N", False)
+    Ad = [x.cuda() for x in As]; Bd = [x.cuda() for x in Bs]
+    C_map = [x.cuda() for x in Cs]
+    with_map = bgemm.Handle()
+    info = with_map.vbatched(Ad, Bd, C_map, ms, ns, ks, 1.0, 0.5, ldas=la, ldbs=lb, ldcs=lc)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(info)) == 0
+    need = with_map._L.bg_workspace_bytes_needed(batch)
+    assert need > 0
+    no_map = bgemm.Handle(workspace_bytes=need)
+    try:
+        C_find = [x.cuda() for x in Cs]
+        info = no_map.vbatched(Ad, Bd, C_find, ms, ns, ks, 1.0, 0.5, ldas=la, ldbs=lb, ldcs=lc)
+        torch.cuda.synchronize()
+        assert int(torch.count_nonzero(info)) == 0
+        for i in range(batch):
+            assert torch.equal(C_find[i].view(torch.int64), C_map[i].view(torch.int64)), i
+        Cref = [c.numpy().copy() for c in Cs]
+        oracle.gemm_vbatched("N", "N", ms, ns, ks, 1.0, [a.numpy() for a in As],
+                             [b.numpy() for b in Bs], 0.5, Cref, ldas=la, ldbs=lb, ldcs=lc)
+        a_rows, a_cols, b_rows, b_cols = shp
+        for i in range(batch):
+            m, n, k = ms[i], ns[i], ks[i]
+            got = C_find[i].cpu().numpy()
+            check_instance(got[:n, :m].T, Cref[i][:n, :m].T,
+                           op_view(As[i].numpy(), a_rows[i], a_cols[i], "N"),
+                           op_view(Bs[i].numpy(), b_rows[i], b_cols[i], "N"),
+                           Cs[i].numpy()[:n, :m].T, 1.0, 0.5, where="inst %d" % i)
+        # one byte short: refused before any launch
+        no_map.set_workspace(need - 1)
+        C_short = [x.cuda() for x in Cs]
+        with pytest.raises(bgemm.BgemmError) as e:
+            no_map.vbatched(Ad, Bd, C_short, ms, ns, ks, 1.0, 0.5, ldas=la, ldbs=lb, ldcs=lc)
+        assert e.value.status == 6          # BG_STATUS_WORKSPACE_TOO_SMALL
+        torch.cuda.synchronize()
+        for i in (0, batch // 2, batch - 1):
+            assert torch.equal(C_short[i].cpu().view(torch.int64), Cs[i].view(torch.int64))
+    finally:
+        no_map.close()
+        with_map.close()

@@ -86,9 +86,11 @@ def test_workload_recipe():
 
 
 def test_bytes_needed():
-    # three n x n binary64 buffers per client, plus two sets (two ticks in
+    # two resident n x n binary64 states per client, a factor pool holding
+    # every client's factor (256-byte aligned), plus two sets (two ticks in
     # flight) of a 32-byte job and three 8-byte pointers
     assert serve.bytes_needed([32, 64]) == 3 * 8 * (32 * 32 + 64 * 64) + 2 * 2 * (32 + 24)
+    assert serve.bytes_needed([7]) == 2 * 8 * 49 + 512 + 2 * (32 + 24)
 
 
 def test_replay_pins():
@@ -131,3 +133,87 @@ def test_limited_active_requests():
         assert np.sum((st <= t) & (fi > t)) <= 3
     with pytest.raises(bgemm.BgemmError):
         serve.simulate(nc, a, c, l, 1e-4, max_active=-1)
+
+
+def _overlap(st, fi, i, j):
+    return st[i] < fi[j] and st[j] < fi[i]
+
+
+@pytest.mark.parametrize("rate", [2000.0, 30000.0])
+def test_lockstep_rounds(rate):
+    """Lock step: requests start only at round boundaries, when no request is
+    active; requests that overlap in time started together; each round lasts
+    its longest chain; requests of one client still run in arrival order."""
+    nc, tick = 16, 1e-4
+    a, c, l = serve.requests(7, nc, rate, 0.05)
+    st, fi, ticks = serve.simulate(nc, a, c, l, tick, policy=serve.POLICY_LOCKSTEP)
+    starts = np.unique(st)
+    for t in starts:
+        rnd = np.nonzero(st == t)[0]
+        # the round ends with its longest chain; nothing else starts before
+        end = t + l[rnd].max() * tick
+        assert np.allclose(fi[rnd], t + l[rnd] * tick)
+        later = st > t
+        assert np.all(st[later] >= end - 1e-9)
+    for i in range(len(a)):
+        assert st[i] >= a[i] - 1e-12
+    for cl in range(nc):
+        idx = np.nonzero(c == cl)[0]
+        assert np.all(np.diff(st[idx]) > 0)
+    # the same arrivals under continuous batching finish no later, on average
+    st2, fi2, ticks2 = serve.simulate(nc, a, c, l, tick)
+    assert (fi2 - a).mean() <= (fi - a).mean()
+    assert ticks2 <= ticks or rate < 5000
+
+
+def test_pool_admission_holds_the_budget():
+    """A factor pool smaller than every client's factor at once: the bytes
+    held by active requests never exceed it, requests wait (counted), every
+    request still completes, and a pool holding every factor gives the same
+    schedule as no pool at all."""
+    sizes = np.array([32, 64, 128, 256, 512, 256, 128, 64], dtype=np.int32)
+    need = sizes.astype(np.int64) ** 2 * 8
+    nc, tick = len(sizes), 1e-4
+    a, c, l = serve.requests(8, nc, 40000.0, 0.02)
+    pool = int(need.max() + need[3])                  # the largest plus one 256^2
+    st, fi, ticks, waits = serve.simulate(nc, a, c, l, tick, sizes=sizes, pool_bytes=pool,
+                                          with_waits=True)
+    assert waits > 0 and np.all(fi > st)
+    for t in np.unique(st):
+        held = (st <= t) & (fi > t)
+        assert need[c[held]].sum() <= pool
+    # no limit from the pool: identical to the unlimited schedule
+    st0, fi0, ticks0 = serve.simulate(nc, a, c, l, tick)
+    st1, fi1, ticks1, w1 = serve.simulate(nc, a, c, l, tick, sizes=sizes,
+                                          pool_bytes=int(need.sum()), with_waits=True)
+    assert w1 == 0 and ticks1 == ticks0
+    assert np.array_equal(st1, st0) and np.array_equal(fi1, fi0)
+    # the tight pool costs time
+    assert fi.max() > fi0.max()
+
+
+def test_pool_oldest_request_is_not_overtaken():
+    # one client of 512 (2 MiB factor) and one of 32; a pool of one 512 factor:
+    # while the first 512 request runs, a 32 request that arrived after a
+    # waiting 512 request must not start before it
+    sizes = [512, 32, 512]
+    need = [512 * 512 * 8, 32 * 32 * 8, 512 * 512 * 8]
+    a = np.array([0.0, 0.0, 0.0])
+    c = np.array([0, 2, 1])
+    l = np.array([3, 1, 1])
+    st, fi, ticks, waits = serve.simulate(3, a, c, l, 1.0, sizes=sizes, pool_bytes=need[0],
+                                          with_waits=True)
+    assert list(st) == [0.0, 3.0, 4.0] and list(fi) == [3.0, 4.0, 5.0] and waits > 0
+
+
+def test_pool_and_policy_argument_errors():
+    a, c, l = np.array([0.0]), np.array([0]), np.array([1])
+    with pytest.raises(bgemm.BgemmError) as e:
+        serve.simulate(1, a, c, l, 1.0, sizes=[64], pool_bytes=64 * 64 * 8 - 1)
+    assert e.value.status == 4
+    with pytest.raises(bgemm.BgemmError) as e:
+        serve.simulate(1, a, c, l, 1.0, policy=2)
+    assert e.value.status == 1
+    with pytest.raises(bgemm.BgemmError) as e:
+        serve.simulate(1, a, c, l, 1.0, pool_bytes=1 << 20)     # a pool needs sizes
+    assert e.value.status == 1
