@@ -100,6 +100,13 @@ struct Cfg {
 #ifndef BG_CLAMPED_LOADS
 #define BG_CLAMPED_LOADS 0
 #endif
+// The pipelined path for any 8-byte-aligned operands and any leading
+// dimension (1: a 16-byte unit then starts at an 8-byte boundary whenever a
+// column starts at one), or only for 16-byte-aligned operands with even
+// leading dimensions (0).
+#ifndef BG_PIPE_ANY_LD
+#define BG_PIPE_ANY_LD 0
+#endif
 // Epilogue C loads all issued before the stores (1), or per element (0).
 #ifndef BG_EPI_BATCH
 #define BG_EPI_BATCH 1
@@ -393,6 +400,9 @@ struct TileSmem {
 __device__ __forceinline__ bool aligned16(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
 }
+__device__ __forceinline__ bool aligned8(const void* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 7) == 0;
+}
 
 // Synchronisation of the threads that share one tile's LDS: the whole
 // workgroup, or (WAVE) one wave that computes a tile on its own.  A wave's LDS
@@ -474,8 +484,10 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
       }
   }
 
-  const bool pipe_ok = CF::PIPE >= 3 && aligned16(A_) && aligned16(B_) && (lda % 2 == 0) &&
-                       (ldb % 2 == 0);
+  const bool pipe_ok = CF::PIPE >= 3 &&
+                       (BG_PIPE_ANY_LD ? (aligned8(A_) && aligned8(B_))
+                                       : (aligned16(A_) && aligned16(B_) && (lda % 2 == 0) &&
+                                          (ldb % 2 == 0)));
   if constexpr (CF::PIPE >= 3) {
     if (use_product && pipe_ok) {
       using PS = PipeSmem<CF, TA, TB>;
