@@ -133,6 +133,36 @@ bg_status_t bg_dgemm_vbatched(bg_handle_t h, char transa, char transb,
                               double* const* dC, const int* d_ldc,
                               int batch, int* d_info);
 
+/* For callers that cannot allocate device memory (work recorded under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * variable-size call of bg_dgemm_vbatched without a handle.  Arguments,
+ * layout, device-side size checks, d_info and results are those of
+ * bg_dgemm_vbatched (bit-identical results); the work is enqueued on
+ * `stream` (a hipStream_t, NULL = default stream) of the CURRENT device.
+ * Nothing is allocated: the planner's buffers live in one static device
+ * array of BG_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs
+ * on until the process ends (its address is looked up on the first call on
+ * that device).  Every call on a GPU reuses that GPU's array and overwrites
+ * it, so calls that may overlap on one GPU (different streams, concurrent
+ * host threads with no ordering between their streams) race and must not be
+ * issued; calls ordered on one stream are safe.  Batches whose planning
+ * buffers do not fit the array (batch > bg_noalloc_max_batch(), about 690,000)
+ * return BG_STATUS_WORKSPACE_TOO_SMALL with nothing enqueued; very large tile
+ * counts are served without the optional tile map (same results).  Host
+ * argument errors return BG_STATUS_INVALID_VALUE and, when bad_arg is not
+ * NULL, set *bad_arg to the argument number of bg_dgemm_vbatched's rules (0
+ * when valid). */
+#define BG_NOALLOC_SCRATCH_BYTES (16u << 20)
+int bg_noalloc_max_batch(void);
+bg_status_t bg_dgemm_vbatched_noalloc(void* stream, char transa, char transb,
+                                      const int* d_m, const int* d_n, const int* d_k,
+                                      double alpha,
+                                      const double* const* dA, const int* d_lda,
+                                      const double* const* dB, const int* d_ldb,
+                                      double beta,
+                                      double* const* dC, const int* d_ldc,
+                                      int batch, int* d_info, int* bad_arg);
+
 /* Arithmetic of bg_gemm_batched_mode.  Inputs and outputs stay binary64; only
  * the arithmetic inside the product changes:
  *   BG_MODE_FP64  the binary64 path of bg_dgemm_batched (slices ignored);

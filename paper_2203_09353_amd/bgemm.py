@@ -28,7 +28,8 @@ EXPORTS = ["bg_version", "bg_status_string", "bg_create", "bg_destroy", "bg_set_
            "bg_get_stream", "bg_set_workspace", "bg_workspace_bytes_needed",
            "bg_last_invalid_arg", "bg_check_batched_args", "bg_dgemm_batched",
            "bg_dgemm_vbatched", "bg_set_uniform_class", "bg_gemm_batched_mode",
-           "bg_zgemm_batched", "bg_zgate2_batched"]
+           "bg_zgemm_batched", "bg_zgate2_batched", "bg_noalloc_max_batch",
+           "bg_dgemm_vbatched_noalloc"]
 
 # bg_mode_t
 MODE_FP64, MODE_FP32, MODE_BF16, MODE_EMU, MODE_EMU_I8, MODE_EMU_F32 = 0, 1, 2, 3, 4, 5
@@ -92,6 +93,11 @@ def lib(path: str | None = None):
     L.bg_zgate2_batched.argtypes = [vp, i, vp, vp, vp, i, vp]
     L.bg_gemm_batched_mode.restype = i
     L.bg_gemm_batched_mode.argtypes = [vp, i, i, c, c, i, i, i, d, vp, i, vp, i, d, vp, i, i]
+    L.bg_noalloc_max_batch.restype = i
+    L.bg_noalloc_max_batch.argtypes = []
+    L.bg_dgemm_vbatched_noalloc.restype = i
+    L.bg_dgemm_vbatched_noalloc.argtypes = [vp, c, c, vp, vp, vp, d, vp, vp, vp, vp, d, vp, vp, i,
+                                            vp, ctypes.POINTER(i)]
     _lib = L
     return L
 
@@ -104,6 +110,18 @@ def check_batched_args(transa, transb, m, n, k, A, lda, B, ldb, C, ldc, batch) -
     """Host-only argument check (no device); 0 or the bad argument's number."""
     return lib().bg_check_batched_args(_ch(transa), _ch(transb), m, n, k, A, lda, B, ldb, C,
                                        ldc, batch)
+
+
+def dgemm_vbatched_noalloc_raw(transa, transb, pm, pn, pk, alpha, pA, plda, pB, pldb, beta, pC,
+                               pldc, batch, pinfo):
+    """bg_dgemm_vbatched_noalloc on torch's current stream of the current
+    device; returns (status, bad argument number)."""
+    bad = ctypes.c_int(-1)
+    st = lib().bg_dgemm_vbatched_noalloc(torch.cuda.current_stream().cuda_stream, _ch(transa),
+                                         _ch(transb), pm, pn, pk, float(alpha), pA, plda, pB,
+                                         pldb, float(beta), pC, pldc, batch, pinfo,
+                                         ctypes.byref(bad))
+    return st, bad.value
 
 
 def pointer_array(x) -> torch.Tensor:

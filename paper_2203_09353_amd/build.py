@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libbgemm.so")
 MICRO_LIB = os.path.join(HERE, "libbgemm_microbench.so")
 ARCH = os.environ.get("BG_OFFLOAD_ARCH", "gfx950")
 SOURCES = [os.path.join(CSRC, f) for f in ("bgemm_api.cpp", "bgemm_kernels.hip", "bgemm_lowp.hip",
-                                           "bgemm_complex.hip", "bgemm_gate.hip", "bgemm_emu8.hip", "serve.cpp",
+                                           "bgemm_complex.hip", "bgemm_gate.hip", "bgemm_emu8.hip", "bgemm_noalloc.hip", "serve.cpp",
                                            "serve_kernels.hip")]
 
 # Packed FP32 instructions are kept out of every device build.

@@ -46,6 +46,46 @@ struct DeviceGuard {
   }
 };
 
+namespace bg {
+
+// Host-side rules of the variable-size call (sizes are checked on the
+// device); returns the argument number of the first bad argument, else 0.
+int vbatched_host_args(char transa, char transb, const int* d_m, const int* d_n, const int* d_k,
+                       const void* dA, const int* d_lda, const void* dB, const int* d_ldb,
+                       const void* dC, const int* d_ldc, int batch) {
+  if (trans_code(transa) < 0) return 1;
+  if (trans_code(transb) < 0) return 2;
+  if (batch < 0) return 14;
+  if (batch > 0) {
+    if (!d_m) return 3;
+    if (!d_n) return 4;
+    if (!d_k) return 5;
+    if (!dA) return 7;
+    if (!d_lda) return 8;
+    if (!dB) return 9;
+    if (!d_ldb) return 10;
+    if (!dC) return 12;
+    if (!d_ldc) return 13;
+  }
+  return 0;
+}
+
+VbatchedArgs vbatched_args(char transa, char transb, const int* d_m, const int* d_n,
+                           const int* d_k, double alpha, const double* const* dA,
+                           const int* d_lda, const double* const* dB, const int* d_ldb,
+                           double beta, double* const* dC, const int* d_ldc, int batch,
+                           int* d_info) {
+  VbatchedArgs a;
+  a.ta = trans_code(transa) == 1; a.tb = trans_code(transb) == 1;
+  a.m = d_m; a.n = d_n; a.k = d_k;
+  a.alpha = alpha; a.beta = beta;
+  a.A = dA; a.lda = d_lda; a.B = dB; a.ldb = d_ldb; a.C = dC; a.ldc = d_ldc;
+  a.batch = batch; a.info = d_info;
+  return a;
+}
+
+}  // namespace bg
+
 extern "C" {
 
 int bg_version(void) { return 100; }
@@ -303,49 +343,13 @@ bg_status_t bg_zgate2_batched(bg_handle_t h, int S, const int* d_site, const dou
              : BG_STATUS_DEVICE_ERROR;
 }
 
-// Host-side rules of the variable-size call (sizes are checked on the
-// device); returns the argument number of the first bad argument, else 0.
-static int vbatched_host_args(char transa, char transb, const int* d_m, const int* d_n,
-                              const int* d_k, const void* dA, const int* d_lda, const void* dB,
-                              const int* d_ldb, const void* dC, const int* d_ldc, int batch) {
-  if (trans_code(transa) < 0) return 1;
-  if (trans_code(transb) < 0) return 2;
-  if (batch < 0) return 14;
-  if (batch > 0) {
-    if (!d_m) return 3;
-    if (!d_n) return 4;
-    if (!d_k) return 5;
-    if (!dA) return 7;
-    if (!d_lda) return 8;
-    if (!dB) return 9;
-    if (!d_ldb) return 10;
-    if (!dC) return 12;
-    if (!d_ldc) return 13;
-  }
-  return 0;
-}
-
-static bg::VbatchedArgs vbatched_args(char transa, char transb, const int* d_m, const int* d_n,
-                                      const int* d_k, double alpha, const double* const* dA,
-                                      const int* d_lda, const double* const* dB, const int* d_ldb,
-                                      double beta, double* const* dC, const int* d_ldc, int batch,
-                                      int* d_info) {
-  bg::VbatchedArgs a;
-  a.ta = trans_code(transa) == 1; a.tb = trans_code(transb) == 1;
-  a.m = d_m; a.n = d_n; a.k = d_k;
-  a.alpha = alpha; a.beta = beta;
-  a.A = dA; a.lda = d_lda; a.B = dB; a.ldb = d_ldb; a.C = dC; a.ldc = d_ldc;
-  a.batch = batch; a.info = d_info;
-  return a;
-}
-
 bg_status_t bg_dgemm_vbatched(bg_handle_t h, char transa, char transb, const int* d_m,
                               const int* d_n, const int* d_k, double alpha,
                               const double* const* dA, const int* d_lda, const double* const* dB,
                               const int* d_ldb, double beta, double* const* dC, const int* d_ldc,
                               int batch, int* d_info) {
   if (!valid(h)) return BG_STATUS_INVALID_HANDLE;
-  const int bad = vbatched_host_args(transa, transb, d_m, d_n, d_k, dA, d_lda, dB, d_ldb, dC,
+  const int bad = bg::vbatched_host_args(transa, transb, d_m, d_n, d_k, dA, d_lda, dB, d_ldb, dC,
                                      d_ldc, batch);
   h->last_invalid_arg = bad;
   if (bad) return BG_STATUS_INVALID_VALUE;
@@ -353,7 +357,7 @@ bg_status_t bg_dgemm_vbatched(bg_handle_t h, char transa, char transb, const int
   if (bg::vbatched_workspace_bytes(batch) > h->ws_bytes) return BG_STATUS_WORKSPACE_TOO_SMALL;
   DeviceGuard guard(h->device);
   if (!guard.ok) return BG_STATUS_DEVICE_ERROR;
-  const bg::VbatchedArgs a = vbatched_args(transa, transb, d_m, d_n, d_k, alpha, dA, d_lda, dB,
+  const bg::VbatchedArgs a = bg::vbatched_args(transa, transb, d_m, d_n, d_k, alpha, dA, d_lda, dB,
                                            d_ldb, beta, dC, d_ldc, batch, d_info);
   bg::VbWorkspace ws{h->ws, h->ws_bytes};
   const hipError_t e = bg::launch_vbatched(a, ws, h->num_cus, h->stream);

@@ -64,6 +64,17 @@ struct VbatchedArgs {
   int* info;  // nullable
 };
 
+// Host-side argument rules of the variable-size call (0 when valid, else the
+// reference-BLAS argument number) and the argument pack built from them.
+int vbatched_host_args(char transa, char transb, const int* d_m, const int* d_n, const int* d_k,
+                       const void* dA, const int* d_lda, const void* dB, const int* d_ldb,
+                       const void* dC, const int* d_ldc, int batch);
+VbatchedArgs vbatched_args(char transa, char transb, const int* d_m, const int* d_n,
+                           const int* d_k, double alpha, const double* const* dA,
+                           const int* d_lda, const double* const* dB, const int* d_ldb,
+                           double beta, double* const* dC, const int* d_ldc, int batch,
+                           int* d_info);
+
 // Workspace layout used by the vbatched planner and executor.
 struct VbWorkspace {
   void* base;
