@@ -285,15 +285,20 @@ def serving_bench(args, h):
         # warm-up: one short schedule
         a, c, l = serve.requests(seed + 100, clients, 2000.0, 0.05)
         srv.run(a, c, l)
-        lockstep_rows = []
+        lockstep_rows, vtick_rows = [], []
         for rate in [float(x) for x in args.rates.split(",")]:
             a, c, l = serve.requests(seed, clients, rate, args.duration)
             # the same arrivals under continuous batching (the paper's tasked
-            # approach) and in lock-step rounds (its batched approach)
-            for policy, out_rows in ((serve.POLICY_CONTINUOUS, rows),
-                                     (serve.POLICY_LOCKSTEP, lockstep_rows)):
+            # approach), in lock-step rounds (its batched approach), and under
+            # continuous batching with each tick issued as one variable-size
+            # launch instead of one uniform launch per client size
+            for policy, tick, out_rows in (
+                    (serve.POLICY_CONTINUOUS, serve.TICK_PER_SIZE, rows),
+                    (serve.POLICY_LOCKSTEP, serve.TICK_PER_SIZE, lockstep_rows),
+                    (serve.POLICY_CONTINUOUS, serve.TICK_VBATCHED, vtick_rows)):
                 srv.reset()
                 srv.set_policy(policy)
+                srv.set_tick_launch(tick)
                 st, fi, ticks = srv.run(a, c, l)
                 pool, peak, waits = srv.memory_stats()
                 n = sizes[c].astype(np.float64)
@@ -309,10 +314,12 @@ def serving_bench(args, h):
                        "ticks": int(ticks), "mean_batch": round(float(l.sum()) / max(ticks, 1), 2),
                        "wall_s": round(wall, 3), "factor_pool_peak_bytes": int(peak),
                        "memory_waits": int(waits)}
-                log(("continuous " if policy == serve.POLICY_CONTINUOUS else "lock step ") +
-                    json.dumps(row))
+                log(("lock step " if policy == serve.POLICY_LOCKSTEP else
+                     "continuous, one variable-size launch per tick " if tick == serve.TICK_VBATCHED
+                     else "continuous ") + json.dumps(row))
                 out_rows.append(row)
             srv.set_policy(serve.POLICY_CONTINUOUS)
+            srv.set_tick_launch(serve.TICK_PER_SIZE)
         # baseline: the same loop serving one request at a time (no batching
         # across clients), on a 0.1 s slice of the highest offered rate
         srv.reset()
@@ -399,7 +406,7 @@ def serving_bench(args, h):
                       "state_sizes": sorted(set(int(x) for x in sizes)),
                       "duration_s": args.duration},
            "roofline": roof, "cpu_baseline": cpu, "rates": rows,
-           "lockstep_rates": lockstep_rows,
+           "lockstep_rates": lockstep_rows, "vbatched_tick_rates": vtick_rows,
            "continuous_vs_lockstep": {
                "throughput_at_top_rate": round(top["achieved_req_s"] /
                                                lockstep_rows[-1]["achieved_req_s"], 3),

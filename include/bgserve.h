@@ -25,7 +25,8 @@
  * queued requests of idle clients (oldest first, as the policy, the active
  * limit and the factor memory allow), and performs one product for every
  * client with an active request: one launch generating all of the tick's
- * factors, then one bg_dgemm_batched launch per distinct size.  A request
+ * factors, then one bg_dgemm_batched launch per distinct size (or one
+ * variable-size launch, bs_set_tick_launch).  A request
  * finishes at the end of the tick of its L-th product.  Two policies:
  *   BS_POLICY_CONTINUOUS  (default) a request starts as soon as its client is
  *                         idle and memory allows: requests that arrive while
@@ -129,6 +130,15 @@ bg_status_t bs_set_policy(bs_server_t s, int policy);
  * memory.  Any pointer may be NULL. */
 bg_status_t bs_memory_stats(bs_server_t s, unsigned long long* pool_bytes,
                             unsigned long long* peak_bytes, long long* waits);
+
+#define BS_TICK_PER_SIZE 0
+#define BS_TICK_VBATCHED 1
+/* How a tick's products are launched: BS_TICK_PER_SIZE (default), one
+ * bg_dgemm_batched per distinct client size; BS_TICK_VBATCHED, one
+ * bg_dgemm_vbatched over every product of the tick (sizes uploaded with the
+ * pointers, planned on the device; it uses the handle's workspace).  Results
+ * are bit-identical either way. */
+bg_status_t bs_set_tick_launch(bs_server_t s, int mode);
 
 /* Limits the number of requests active at once (0, the default: no limit,
  * every client with queued work is served at every tick).  With a limit,

@@ -231,10 +231,15 @@ struct bs_server {
   bg::FillJob* h_jobs[2];         // pinned
   const double** d_ptrs[2];
   const double** h_ptrs[2];       // pinned
+  // per-instance sizes and leading dimensions of a tick's variable-size
+  // launch: m, n, k, lda, ldb, ldc, each num_clients ints
+  int* d_dims[2];
+  int* h_dims[2];                  // pinned
   hipEvent_t ev[2];
   hipEvent_t ev0;
   int max_active;
   int policy;
+  int tick_launch;                // BS_TICK_PER_SIZE or BS_TICK_VBATCHED
   long long mem_waits;            // of the last bs_run_schedule
 };
 
@@ -243,7 +248,9 @@ static bool valid(bs_server_t s) { return s && s->magic == kServerMagic; }
 
 static size_t state_bytes(int n) { return 2 * (size_t)n * (size_t)n * sizeof(double); }
 static size_t factor_bytes(int n) { return bs::Pool::round((size_t)n * (size_t)n * sizeof(double)); }
-static size_t array_bytes(int nc) { return 2ull * nc * (sizeof(bg::FillJob) + 3 * sizeof(double*)); }
+static size_t array_bytes(int nc) {
+  return 2ull * nc * (sizeof(bg::FillJob) + 3 * sizeof(double*) + 6 * sizeof(int));
+}
 
 static void free_all(bs_server* s) {
   for (int b = 0; b < 2; ++b)
@@ -254,6 +261,8 @@ static void free_all(bs_server* s) {
     if (s->d_ptrs[b]) (void)hipFree((void*)s->d_ptrs[b]);
     if (s->h_jobs[b]) (void)hipHostFree(s->h_jobs[b]);
     if (s->h_ptrs[b]) (void)hipHostFree((void*)s->h_ptrs[b]);
+    if (s->d_dims[b]) (void)hipFree(s->d_dims[b]);
+    if (s->h_dims[b]) (void)hipHostFree(s->h_dims[b]);
     if (s->ev[b]) (void)hipEventDestroy(s->ev[b]);
   }
   if (s->ev0) (void)hipEventDestroy(s->ev0);
@@ -312,6 +321,7 @@ bg_status_t bs_create(bg_handle_t h, int num_clients, const int* sizes, unsigned
   s->pool_bytes = pool_bytes;
   s->need.resize(num_clients);
   s->policy = 0;
+  s->tick_launch = BS_TICK_PER_SIZE;
   s->mem_waits = 0;
   s->cur.assign(num_clients, 0);
   s->products.assign(num_clients, 0);
@@ -328,6 +338,8 @@ bg_status_t bs_create(bg_handle_t h, int num_clients, const int* sizes, unsigned
          hipMalloc((void**)&s->d_ptrs[b], 3 * num_clients * sizeof(double*)) == hipSuccess &&
          hipHostMalloc((void**)&s->h_jobs[b], num_clients * sizeof(bg::FillJob)) == hipSuccess &&
          hipHostMalloc((void**)&s->h_ptrs[b], 3 * num_clients * sizeof(double*)) == hipSuccess &&
+         hipMalloc((void**)&s->d_dims[b], 6 * num_clients * sizeof(int)) == hipSuccess &&
+         hipHostMalloc((void**)&s->h_dims[b], 6 * num_clients * sizeof(int)) == hipSuccess &&
          hipEventCreate(&s->ev[b]) == hipSuccess;
   ok = ok && hipEventCreate(&s->ev0) == hipSuccess;
   if (!ok) {
@@ -387,6 +399,13 @@ bg_status_t bs_fill_factor(unsigned long long seed, int c, long long j, int n, d
                  hipSuccess
              ? BG_STATUS_SUCCESS
              : BG_STATUS_DEVICE_ERROR;
+}
+
+bg_status_t bs_set_tick_launch(bs_server_t s, int mode) {
+  if (!valid(s)) return BG_STATUS_INVALID_HANDLE;
+  if (mode != BS_TICK_PER_SIZE && mode != BS_TICK_VBATCHED) return BG_STATUS_INVALID_VALUE;
+  s->tick_launch = mode;
+  return BG_STATUS_SUCCESS;
 }
 
 bg_status_t bs_set_max_active(bs_server_t s, int max_active) {
@@ -545,15 +564,31 @@ bg_status_t bs_run_schedule(bs_server_t s, int n_requests, const double* arrival
                        hipMemcpyHostToDevice, stream) != hipSuccess ||
         bg::launch_fill_factors(s->d_jobs[set], nb, max_n, s->seed, stream) != hipSuccess)
       return BG_STATUS_DEVICE_ERROR;
-    for (int g0 = 0; g0 < nb;) {
-      int g1 = g0;
-      const int n = s->sizes[order[g0]];
-      while (g1 < nb && s->sizes[order[g1]] == n) ++g1;
-      const bg_status_t st = bg_dgemm_batched(s->h, 'N', 'N', n, n, n, 1.0, dp + g0, n,
-                                              dp + nb + g0, n, 0.0,
-                                              (double* const*)(dp + 2 * nb + g0), n, g1 - g0);
+    if (s->tick_launch == BS_TICK_VBATCHED) {
+      // one variable-size launch for the whole tick, planned on the device
+      int* hd = s->h_dims[set];
+      int* dd = s->d_dims[set];
+      for (int f = 0; f < 6; ++f)
+        for (int i = 0; i < nb; ++i) hd[f * nb + i] = s->sizes[order[i]];
+      if (hipMemcpyAsync(dd, hd, 6 * nb * sizeof(int), hipMemcpyHostToDevice, stream) !=
+          hipSuccess)
+        return BG_STATUS_DEVICE_ERROR;
+      const bg_status_t st =
+          bg_dgemm_vbatched(s->h, 'N', 'N', dd, dd + nb, dd + 2 * nb, 1.0, dp, dd + 3 * nb,
+                            dp + nb, dd + 4 * nb, 0.0, (double* const*)(dp + 2 * nb),
+                            dd + 5 * nb, nb, nullptr);
       if (st != BG_STATUS_SUCCESS) return st;
-      g0 = g1;
+    } else {
+      for (int g0 = 0; g0 < nb;) {
+        int g1 = g0;
+        const int n = s->sizes[order[g0]];
+        while (g1 < nb && s->sizes[order[g1]] == n) ++g1;
+        const bg_status_t st = bg_dgemm_batched(s->h, 'N', 'N', n, n, n, 1.0, dp + g0, n,
+                                                dp + nb + g0, n, 0.0,
+                                                (double* const*)(dp + 2 * nb + g0), n, g1 - g0);
+        if (st != BG_STATUS_SUCCESS) return st;
+        g0 = g1;
+      }
     }
     if (hipEventRecord(s->ev[set], stream) != hipSuccess) return BG_STATUS_DEVICE_ERROR;
     for (int c : sc.batch) {

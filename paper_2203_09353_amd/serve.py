@@ -54,6 +54,8 @@ def _lib():
         L.bs_run_sweeps.argtypes = [vp, i, i, i, ctypes.POINTER(d)]
         L.bs_set_max_active.restype = i
         L.bs_set_max_active.argtypes = [vp, i]
+        L.bs_set_tick_launch.restype = i
+        L.bs_set_tick_launch.argtypes = [vp, i]
         _set = True
     return L
 
@@ -72,6 +74,7 @@ def bytes_needed(sizes) -> int:
 
 
 POLICY_CONTINUOUS, POLICY_LOCKSTEP = 0, 1
+TICK_PER_SIZE, TICK_VBATCHED = 0, 1
 
 
 def simulate(num_clients, arrivals, clients, lengths, tick_s, max_active=0,
@@ -144,6 +147,13 @@ class Server:
         r = self.L.bs_set_max_active(self._s, int(k))
         if r != 0:
             raise bgemm.BgemmError("bs_set_max_active", r)
+
+    def set_tick_launch(self, mode: int):
+        """TICK_PER_SIZE (default: one batched launch per client size) or
+        TICK_VBATCHED (one variable-size launch per tick)."""
+        r = self.L.bs_set_tick_launch(self._s, int(mode))
+        if r != 0:
+            raise bgemm.BgemmError("bs_set_tick_launch", r)
 
     def set_policy(self, policy: int):
         """POLICY_CONTINUOUS (default) or POLICY_LOCKSTEP."""

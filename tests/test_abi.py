@@ -33,7 +33,7 @@ def test_library_exports_the_request_loop():
     assert declared == {"bs_create", "bs_destroy", "bs_bytes_needed", "bs_reset",
                         "bs_run_schedule", "bs_state", "bs_fill_factor", "bs_simulate",
                         "bs_set_max_active", "bs_run_sweeps", "bs_set_policy",
-                        "bs_memory_stats"}
+                        "bs_memory_stats", "bs_set_tick_launch"}
     for name in declared:
         assert hasattr(L, name), name
     # host-side argument checks need no device
@@ -42,6 +42,7 @@ def test_library_exports_the_request_loop():
     assert L.bs_fill_factor(1, 0, 0, 0, None, None) == 1
     assert L.bs_set_policy(None, 1) == 5
     assert L.bs_memory_stats(None, None, None, None) == 5
+    assert L.bs_set_tick_launch(None, 1) == 5
 
 
 def test_version_and_status_strings():

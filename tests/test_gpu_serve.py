@@ -197,3 +197,31 @@ def test_lockstep_and_tight_memory_give_the_same_states(h):
                 assert p == pw and np.array_equal(S.view(np.int64), W.view(np.int64)), (policy, cl)
         finally:
             srv.close()
+
+
+def test_one_variable_size_launch_per_tick_gives_the_same_states(h):
+    """Ticks issued as one bg_dgemm_vbatched over every product (instead of
+    one bg_dgemm_batched per client size) compute the same products: final
+    states are bit-identical, under both policies."""
+    a, c, l = _schedule()
+    ref = serve.Server(h, SIZES, seed=41)
+    try:
+        ref.run(a, c, l)
+        want = {cl: ref.state(cl) for cl in range(len(SIZES))}
+    finally:
+        ref.close()
+    for policy in (serve.POLICY_CONTINUOUS, serve.POLICY_LOCKSTEP):
+        srv = serve.Server(h, SIZES, seed=41)
+        try:
+            with pytest.raises(bgemm.BgemmError):
+                srv.set_tick_launch(2)
+            srv.set_tick_launch(serve.TICK_VBATCHED)
+            srv.set_policy(policy)
+            st, fi, ticks = srv.run(a, c, l)
+            assert np.all(st >= a) and np.all(fi > st)
+            for cl in range(len(SIZES)):
+                S, p = srv.state(cl)
+                W, pw = want[cl]
+                assert p == pw and np.array_equal(S.view(np.int64), W.view(np.int64)), (policy, cl)
+        finally:
+            srv.close()

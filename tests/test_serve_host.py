@@ -88,9 +88,9 @@ def test_workload_recipe():
 def test_bytes_needed():
     # two resident n x n binary64 states per client, a factor pool holding
     # every client's factor (256-byte aligned), plus two sets (two ticks in
-    # flight) of a 32-byte job and three 8-byte pointers
-    assert serve.bytes_needed([32, 64]) == 3 * 8 * (32 * 32 + 64 * 64) + 2 * 2 * (32 + 24)
-    assert serve.bytes_needed([7]) == 2 * 8 * 49 + 512 + 2 * (32 + 24)
+    # flight) of a 32-byte job, three 8-byte pointers and six 4-byte sizes
+    assert serve.bytes_needed([32, 64]) == 3 * 8 * (32 * 32 + 64 * 64) + 2 * 2 * (32 + 24 + 24)
+    assert serve.bytes_needed([7]) == 2 * 8 * 49 + 512 + 2 * (32 + 24 + 24)
 
 
 def test_replay_pins():
