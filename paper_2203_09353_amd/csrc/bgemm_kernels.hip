@@ -404,35 +404,16 @@ __device__ __forceinline__ bool aligned8(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 7) == 0;
 }
 
-// Synchronisation of the threads that share one tile's LDS: the whole
-// workgroup, or (WAVE) one wave that computes a tile on its own.  A wave's LDS
-// instructions are performed in issue order; the fence makes the compiler
-// keep them in program order and waits for this wave's outstanding LDS
-// accesses, so no other wave needs to take part.
-template <bool WAVE>
-__device__ __forceinline__ void tile_sync() {
-  if constexpr (WAVE) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  } else {
-    __syncthreads();
-  }
-}
-
 // ---------------------------------------------------------------------------
 // One C tile (tm, tn) of one instance.  M, N, K are the sizes of op(A) (M x K)
 // and op(B) (K x N).  use_product == false means alpha == 0 or K == 0: A and B
 // are not read and C <- beta * C (exactly 0 when beta == 0, untouched when
-// beta == 1).  Every thread of the workgroup must call this (it synchronises);
-// with WAVE, one wave computes the tile alone (CF::NT == 64, register path,
-// `lds` private to the wave) and only that wave calls it.
+// beta == 1).  Every thread of the workgroup must call this (it synchronises).
 // ---------------------------------------------------------------------------
-template <class CF, bool TA, bool TB, bool WAVE = false>
+template <class CF, bool TA, bool TB>
 __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const double* B_,
                                           int64_t ldb, double* C_, int64_t ldc, int M, int N, int K,
                                           double alpha, double beta, int tm, int tn, lptr lds) {
-  static_assert(!WAVE || (CF::NT == 64 && CF::PIPE == 0), "a wave-local tile is one wave, register path");
   const gcptr A = (gcptr)A_;
   const gcptr B = (gcptr)B_;
   const gptr C = (gptr)C_;
@@ -444,11 +425,10 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
   constexpr bool SW = CF::SWAP;
   // The thread id passes through an opaque move, so that the lane-dependent
   // LDS and global offsets below are computed inside this tile rather than
-  // hoisted out of a persistent caller's loop (where the offsets of every
-  // tile shape it runs would stay live at once).
-  int tid_raw;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(tid_raw) : "v"((int)threadIdx.x));
-  const int tid = WAVE ? (tid_raw & 63) : tid_raw;
+  // hoisted out of a persistent caller's tile loop, where they would stay
+  // live (in registers) across every tile.
+  int tid;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
   const int lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave % CF::WAVES_M) * CF::WM;
   const int wn0 = (wave / CF::WAVES_M) * CF::WN;
@@ -593,7 +573,7 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
     load(0);
     ra.store(la0, tid);
     rb.store(lb0, tid);
-    tile_sync<WAVE>();
+    __syncthreads();
     const int p0 = SW ? wn0 : wm0, q0 = SW ? wm0 : wn0;
     // Valid extents of this wave's region along P and Q.  On edge tiles the
     // instructions whose 16 P indices or 4 Q indices all fall outside C are
@@ -642,12 +622,12 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
         }
       }
       if (kt + 1 < nk) {
-        if (CF::NSTAGE == 1) tile_sync<WAVE>();  // every wave is done reading the stage
+        if (CF::NSTAGE == 1) __syncthreads();  // every wave is done reading the stage
         const int nxt = CF::NSTAGE == 2 ? (cur ^ 1) : 0;
         ra.store(la0 + nxt * SM::A_ELEMS, tid);
         rb.store(lb0 + nxt * SM::B_ELEMS, tid);
       }
-      tile_sync<WAVE>();
+      __syncthreads();
     }
   }
 
@@ -824,10 +804,6 @@ hipError_t launch_scale(double beta, double* const* C, int64_t ldc, int m, int n
 #endif
 #ifndef BG_CFGVB_S
 #define BG_CFGVB_S 32, 32, 16, 32, 32, false, 2, true
-#endif
-// one fused persistent grid for all classes (1), or one grid per class (0)
-#ifndef BG_VB_FUSED
-#define BG_VB_FUSED 0
 #endif
 // relative cost per padded C element of the three classes, for the choice
 #ifndef BG_VB_WEIGHTS
@@ -1059,218 +1035,6 @@ __global__ __launch_bounds__(CF::NT) void k_vb_exec(
   }
 }
 
-// ---------------------------------------------------------------------------
-// Fused executor: one persistent grid for every class.  Its workgroups have
-// the large class's NW waves; a work item is an L tile or an M tile (the whole
-// workgroup computes it) or an S group: NW consecutive S tiles, one per wave,
-// each wave synchronising on its own, so that many small, memory-bound tiles
-// are in flight at once.  Items come from one queue in one of two orders:
-//   largest first -- all L tiles, then the M tiles, then the S groups;
-//   interleaved   -- the three lists merged so that each class advances at
-//                    the same fraction of its own items at every point of the
-//                    queue (item t of a class with N items has key
-//                    (2t + 1) / 2N; ties go to the smaller class number), so
-//                    memory-bound small tiles run beside matrix-core-bound
-//                    large ones instead of after them.
-// The interleaved order is written by k_vb_order into the workspace after the
-// tile map; when the two do not fit, the queue is largest first.
-// ---------------------------------------------------------------------------
-#ifndef BG_CFGVB_M8
-#define BG_CFGVB_M8 64, 64, 16, 16, 32, true
-#endif
-#ifndef BG_CFGVB_S1
-#define BG_CFGVB_S1 32, 32, 16, 32, 32, true, 1
-#endif
-#ifndef BG_VB_ORDER
-#define BG_VB_ORDER 1   // 0 largest first, 1 interleaved
-#endif
-// waves per SIMD the fused kernel's register budget must allow
-#ifndef BG_VB_FUSED_WAVES
-#define BG_VB_FUSED_WAVES 4
-#endif
-using CfgVbM8 = Cfg<BG_CFGVB_M8>;
-using CfgVbS1 = Cfg<BG_CFGVB_S1>;
-constexpr int VB_NW = CfgVbL::NT / 64;   // waves per workgroup = S tiles per S group
-static_assert(CfgVbM8::NT == CfgVbL::NT, "L and M tiles use the whole workgroup");
-static_assert(CfgVbS1::NT == 64, "an S tile is computed by one wave");
-static_assert(CfgVbM8::BM == CfgVbM::BM && CfgVbM8::BN == CfgVbM::BN &&
-              CfgVbS1::BM == CfgVbS::BM && CfgVbS1::BN == CfgVbS::BN,
-              "the planner counts tiles with the class shapes");
-constexpr int ORDER_TBITS = 29;          // order entry: class << 29 | item index
-
-// Items per class of the fused queue (L tiles, M tiles, S groups).
-__device__ __forceinline__ void vb_items(const int64_t* ctrl, int64_t n[VB_NC]) {
-  n[0] = ctrl[0];
-  n[1] = ctrl[1];
-  n[2] = (ctrl[2] + VB_NW - 1) / VB_NW;
-}
-
-// Whether the workspace after the planner holds the tile map (every tile of
-// every class) and, after it, the interleaved item order.
-__device__ __forceinline__ bool vb_map_fits(const int64_t* ctrl, int64_t cap) {
-  return ctrl[0] + ctrl[1] + ctrl[2] <= cap;
-}
-__device__ __forceinline__ bool vb_order_fits(const int64_t* ctrl, int64_t cap) {
-  int64_t n[VB_NC];
-  vb_items(ctrl, n);
-  const int64_t lim = (int64_t)1 << ORDER_TBITS;
-  return BG_VB_ORDER == 1 && n[0] < lim && n[1] < lim && n[2] < lim &&
-         ctrl[0] + ctrl[1] + ctrl[2] + n[0] + n[1] + n[2] <= cap;
-}
-
-// Number of items j of a class with n_other items that come before item t of
-// a class with n_self items: (2j + 1) n_self < (2t + 1) n_other, or equal
-// when the other class comes first on ties.
-__device__ __forceinline__ int64_t vb_before(int64_t n_other, int64_t n_self, int64_t t,
-                                             bool other_first) {
-  if (n_other == 0) return 0;
-  const int64_t x = (2 * t + 1) * n_other;
-  const int64_t q = (x + n_self - 1) / n_self;        // odd o with o n_self < x: floor(q / 2)
-  int64_t cnt = q / 2;
-  if (other_first && x % n_self == 0 && ((x / n_self) & 1)) ++cnt;
-  return cnt < n_other ? cnt : n_other;
-}
-
-__global__ __launch_bounds__(256) void k_vb_order(const int64_t* __restrict__ ctrl,
-                                                  int* __restrict__ ws_int, int64_t cap) {
-  if (!vb_order_fits(ctrl, cap)) return;
-  int64_t n[VB_NC];
-  vb_items(ctrl, n);
-  int* order = ws_int + (ctrl[0] + ctrl[1] + ctrl[2]);
-  const int64_t total = n[0] + n[1] + n[2];
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
-       u += (int64_t)gridDim.x * blockDim.x) {
-    const int c = u < n[0] ? 0 : (u < n[0] + n[1] ? 1 : 2);
-    const int64_t t = u - (c >= 1 ? n[0] : 0) - (c == 2 ? n[1] : 0);
-    int64_t pos = t;
-    for (int o = 0; o < VB_NC; ++o)
-      if (o != c) pos += vb_before(n[o], n[c], t, o < c);
-    order[pos] = (c << ORDER_TBITS) | (int)t;
-  }
-}
-
-template <class CL, class CM, class CS, bool TA, bool TB>
-struct FusedSmem {
-  static constexpr int l = TileSmem<CL, TA, TB>::TOTAL;
-  static constexpr int m = TileSmem<CM, TA, TB>::TOTAL;
-  static constexpr int s1 = TileSmem<CS, TA, TB>::TOTAL;   // one wave's S tile
-  static constexpr int s = VB_NW * s1;
-  static constexpr int lm = l > m ? l : m;
-  static constexpr int TOTAL = lm > s ? lm : s;
-};
-
-// One tile of a class of the fused kernel, from its index within the instance.
-template <class CF, bool TA, bool TB, bool WAVE>
-__device__ __forceinline__ void vb_tile(const double* A, int64_t lda, const double* B, int64_t ldb,
-                                     double* C, int64_t ldc, int M, int N, int K, double alpha,
-                                     double beta, int lt, lptr lds) {
-  const int tiles_m = (M + CF::BM - 1) / CF::BM;
-  gemm_tile<CF, TA, TB, WAVE>(A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, lt % tiles_m,
-                              lt / tiles_m, lds);
-}
-
-template <class CL, class CM, class CS, bool TA, bool TB>
-__global__ __launch_bounds__(CL::NT, BG_VB_FUSED_WAVES) void k_vb_fused(
-    const int* __restrict__ m, const int* __restrict__ n, const int* __restrict__ k, double alpha,
-    const double* const* __restrict__ Ap, const int* __restrict__ lda,
-    const double* const* __restrict__ Bp, const int* __restrict__ ldb, double beta,
-    double* const* __restrict__ Cp, const int* __restrict__ ldc, int batch,
-    const int64_t* __restrict__ prefix_all, int64_t* __restrict__ ctrl,
-    const int* __restrict__ ws_int, int64_t cap) {
-  using SM = FusedSmem<CL, CM, CS, TA, TB>;
-  __shared__ double lds[SM::TOTAL];
-  __shared__ int64_t s_q;
-  int64_t nit[VB_NC];
-  vb_items(ctrl, nit);
-  const int64_t total = nit[0] + nit[1] + nit[2];
-  const int64_t t_l = ctrl[0], t_m = ctrl[1], t_s = ctrl[2];
-  const bool use_map = vb_map_fits(ctrl, cap);
-  const bool use_order = vb_order_fits(ctrl, cap);
-  const int* order = ws_int + (t_l + t_m + t_s);
-  // instance owning tile t of class c
-  auto owner = [&](int c, int64_t t) -> int {
-    const int64_t moff = (c >= 1 ? t_l : 0) + (c == 2 ? t_m : 0);
-    return use_map ? ws_int[moff + t] : vb_find(prefix_all + (int64_t)c * (batch + 1), batch, t);
-  };
-  unsigned long long* heads = (unsigned long long*)&ctrl[VB_NC];
-  const int home = blockIdx.x % NUM_XCD;
-  for (int step = 0; step < NUM_XCD; ++step) {
-    const int x = (home + step) % NUM_XCD;
-    const int64_t lo = total * x / NUM_XCD, hi = total * (x + 1) / NUM_XCD;
-    for (;;) {
-      if (threadIdx.x == 0) s_q = lo + (int64_t)atomicAdd(&heads[x], 1ull);
-      __syncthreads();
-      const int64_t q = s_q;
-      __syncthreads();
-      if (q >= hi) break;
-      int c;
-      int64_t t;
-      if (use_order) {
-        const int v = order[q];
-        c = v >> ORDER_TBITS;
-        t = v & ((1 << ORDER_TBITS) - 1);
-        // k_vb_order writes a permutation of the items; an entry outside the
-        // item ranges is skipped rather than trusted
-        if (c < 0 || c >= VB_NC || t >= nit[c < VB_NC ? c : 0]) {
-          __syncthreads();
-          continue;
-        }
-      } else {
-        c = q < nit[0] ? 0 : (q < nit[0] + nit[1] ? 1 : 2);
-        t = q - (c >= 1 ? nit[0] : 0) - (c == 2 ? nit[1] : 0);
-      }
-      if (c == 0) {
-        const int i = owner(0, t);
-        vb_tile<CL, TA, TB, false>(Ap[i], lda[i], Bp[i], ldb[i], Cp[i], ldc[i], m[i], n[i], k[i],
-                                   alpha, beta, (int)(t - prefix_all[i]), (lptr)lds);
-      } else if (c == 1) {
-        const int i = owner(1, t);
-        vb_tile<CM, TA, TB, false>(Ap[i], lda[i], Bp[i], ldb[i], Cp[i], ldc[i], m[i], n[i], k[i],
-                                   alpha, beta, (int)(t - prefix_all[(int64_t)(batch + 1) + i]),
-                                   (lptr)lds);
-      } else {
-        const int w = threadIdx.x >> 6;
-        const int64_t ts = t * VB_NW + w;
-        if (ts < t_s) {
-          const int i = owner(2, ts);
-          vb_tile<CS, TA, TB, true>(Ap[i], lda[i], Bp[i], ldb[i], Cp[i], ldc[i], m[i], n[i], k[i],
-                                    alpha, beta,
-                                    (int)(ts - prefix_all[2 * (int64_t)(batch + 1) + i]),
-                                    (lptr)lds + w * SM::s1);
-        }
-      }
-      __syncthreads();  // LDS free for the next item
-    }
-  }
-}
-
-template <bool TA, bool TB>
-static hipError_t launch_vb_fused_t(const VbatchedArgs& a, const VbLayout& L, int num_cus,
-                                    hipStream_t s) {
-  auto kern = k_vb_fused<CfgVbL, CfgVbM8, CfgVbS1, TA, TB>;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, CfgVbL::NT, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  hipLaunchKernelGGL(kern, dim3(num_cus * per_cu), dim3(CfgVbL::NT), 0, s, a.m, a.n, a.k, a.alpha,
-                     a.A, a.lda, a.B, a.ldb, a.beta, a.C, a.ldc, a.batch, L.prefix, L.ctrl, L.map,
-                     L.map_cap);
-  return hipGetLastError();
-}
-
-static hipError_t launch_vb_fused(const VbatchedArgs& a, const VbLayout& L, int num_cus,
-                                  hipStream_t s) {
-  if (BG_VB_ORDER == 1) {
-    hipLaunchKernelGGL(k_vb_order, dim3(1024), dim3(256), 0, s, L.ctrl, L.map, L.map_cap);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (!a.ta && !a.tb) return launch_vb_fused_t<false, false>(a, L, num_cus, s);
-  if (!a.ta && a.tb) return launch_vb_fused_t<false, true>(a, L, num_cus, s);
-  if (a.ta && !a.tb) return launch_vb_fused_t<true, false>(a, L, num_cus, s);
-  return launch_vb_fused_t<true, true>(a, L, num_cus, s);
-}
-
 template <class CF, bool TA, bool TB>
 static hipError_t launch_vb_exec(const VbatchedArgs& a, const VbLayout& L, int cls, int num_cus,
                                  hipStream_t s) {
@@ -1309,7 +1073,6 @@ hipError_t launch_vbatched(const VbatchedArgs& a, const VbWorkspace& ws, int num
                      L.map_cap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (BG_VB_FUSED) return launch_vb_fused(a, L, num_cus, s);
   if ((e = launch_vb_exec_t<CfgVbL>(a, L, 0, num_cus, s)) != hipSuccess) return e;
   if ((e = launch_vb_exec_t<CfgVbM>(a, L, 1, num_cus, s)) != hipSuccess) return e;
   return launch_vb_exec_t<CfgVbS>(a, L, 2, num_cus, s);
