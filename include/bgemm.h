@@ -14,12 +14,14 @@
  * (lda >= max(1, k)).  B with 'N' is stored k x n (ldb >= max(1, k)); with 'T'
  * n x k (ldb >= max(1, n)).  ldc >= max(1, m).  Rows r >= rows of a column
  * (the ld padding) are never written, and their values never reach a stored
- * result.  They may be read: when a leading dimension is even and the
- * column length odd, a 16-byte load at the end of a column can take the
- * first padding element with it; that element only enters products for C
- * rows or columns outside C, which are discarded.  The padding must therefore
- * be readable memory (it is, by ld >= rows), but its contents (NaN included)
- * never matter.
+ * result.  They may be read: when a column length is odd, a 16-byte load at
+ * the end of a column (other than the last column of the matrix) can take
+ * the element after it with it -- the first padding element, or the next
+ * column's first element when ld equals the column length; that element
+ * only enters products for C rows or columns outside C, which are
+ * discarded.  The padding must therefore be readable memory (it is, by
+ * ld >= rows), but its contents (NaN included) never matter.  Operands need
+ * 8-byte alignment.
  *
  * Memory and ownership.  Matrices, the pointer arrays dA/dB/dC (one device
  * pointer per instance), the per-instance size arrays of the variable-size
@@ -86,8 +88,10 @@ bg_status_t bg_set_stream(bg_handle_t h, void* stream);
 bg_status_t bg_get_stream(bg_handle_t h, void** stream);
 
 /* Replaces the workspace with one of `bytes` bytes (synchronises the stream).
- * The variable-size call needs about 8 * (batch + 1) + 8 * batch / 256 bytes of
- * planning space plus, for its fastest schedule, 4 bytes per C tile. */
+ * The variable-size call needs bg_workspace_bytes_needed(batch) bytes of
+ * planning space (about 24 * (batch + 1) bytes of prefix sums plus 96 KiB of
+ * queue heads, each on its own 4 KiB line) plus, for its fastest schedule,
+ * 4 bytes per C tile. */
 bg_status_t bg_set_workspace(bg_handle_t h, unsigned long long bytes);
 unsigned long long bg_workspace_bytes_needed(int batch);
 

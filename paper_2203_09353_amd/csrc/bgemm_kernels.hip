@@ -65,8 +65,10 @@ struct Cfg {
   static constexpr bool SWAP = SWAP_;
   static constexpr int NSTAGE = NSTAGE_;      // LDS buffers (2: double buffered)
   static constexpr bool CPRE = CPRE_;         // read C (beta != 0) before the k loop
-  // Work skipped on edge tiles: 0 none, 1 waves whose region lies outside C,
-  // 2 also single instructions whose 16 x 4 output lies outside C.
+  // Work skipped on edge tiles: 0 none, 1 waves whose region lies outside C
+  // (on the pipelined path also the 16-wide P slabs outside C), 2 on the
+  // register path also single instructions whose 16 x 4 output lies outside
+  // C.
   static constexpr int SKIP = SKIP_;
   // PIPE >= 3: instances whose A and B are 16-byte aligned with even leading
   // dimensions use the pipelined path, a ring of PIPE LDS stages filled by
@@ -105,7 +107,7 @@ struct Cfg {
 // column starts at one), or only for 16-byte-aligned operands with even
 // leading dimensions (0).
 #ifndef BG_PIPE_ANY_LD
-#define BG_PIPE_ANY_LD 0
+#define BG_PIPE_ANY_LD 1
 #endif
 // Epilogue C loads all issued before the stores (1), or per element (0).
 #ifndef BG_EPI_BATCH
@@ -506,9 +508,12 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
       // Step kt lives in stage kt mod NS.  Its loads are complete once at most
       // (steps issued after it) x DPT of this wave's loads remain; loads
       // return in order.  The barrier then publishes every wave's part, and
-      // only after it is the stage read one step earlier refilled.
-      auto step = [&](int kt, auto stage_c) {
+      // only after it is the stage read one step earlier refilled.  NPA of
+      // the wave's FP slabs along P take part in the products (fewer on edge
+      // tiles, see below); every wave issues the same loads and barriers.
+      auto step = [&](int kt, auto stage_c, auto npa_c) {
         constexpr int st = decltype(stage_c)::value;
+        constexpr int NPA = decltype(npa_c)::value;
         const int pending = min(NS - 2, nk - 1 - kt);
         asm volatile("" ::: "memory");
         if (pending <= 0) __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
@@ -521,36 +526,61 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
         const lcptr la = lds + st * PS::STAGE, lb = la + TAs::ELEMS;
         const lcptr lp = SW ? lb : la;
         const lcptr lq = SW ? la : lb;
+        if constexpr (NPA > 0) {
 #pragma unroll
-        for (int kk = 0; kk < CF::BK; kk += 16) {
-          if (kt * CF::BK + kk >= K) break;  // whole 16-slices only, as on the other path
+          for (int kk = 0; kk < CF::BK; kk += 16) {
+            if (kt * CF::BK + kk >= K) break;  // whole 16-slices only, as on the other path
 #pragma unroll
-          for (int tp = 0; tp < 2; ++tp) {
-            double fp[CF::FP][2], fq[CF::GQ][2];
-            if constexpr (SW) {
-              read_p_sw<TBs, CF::FP, !TB>(lp, p0, kk, tp, lane, fp);
-              read_q_sw<TAs, CF::GQ, TA>(lq, q0, kk, tp, lane, fq);
-            } else {
-              read_p_sw<TAs, CF::FP, TA>(lp, p0, kk, tp, lane, fp);
-              read_q_sw<TBs, CF::GQ, !TB>(lq, q0, kk, tp, lane, fq);
+            for (int tp = 0; tp < 2; ++tp) {
+              double fp[NPA][2], fq[CF::GQ][2];
+              if constexpr (SW) {
+                read_p_sw<TBs, NPA, !TB>(lp, p0, kk, tp, lane, fp);
+                read_q_sw<TAs, CF::GQ, TA>(lq, q0, kk, tp, lane, fq);
+              } else {
+                read_p_sw<TAs, NPA, TA>(lp, p0, kk, tp, lane, fp);
+                read_q_sw<TBs, CF::GQ, !TB>(lq, q0, kk, tp, lane, fq);
+              }
+#pragma unroll
+              for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int i = 0; i < NPA; ++i)
+#pragma unroll
+                  for (int j = 0; j < CF::GQ; ++j)
+                    acc[i][j] =
+                        __builtin_amdgcn_mfma_f64_4x4x4f64(fp[i][u], fq[j][u], acc[i][j], 0, 0, 0);
             }
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-              for (int i = 0; i < CF::FP; ++i)
-#pragma unroll
-                for (int j = 0; j < CF::GQ; ++j)
-                  acc[i][j] =
-                      __builtin_amdgcn_mfma_f64_4x4x4f64(fp[i][u], fq[j][u], acc[i][j], 0, 0, 0);
           }
         }
       };
-      for (int kt0 = 0; kt0 < nk; kt0 += NS) {
-        step(kt0, std::integral_constant<int, 0>{});
-        if (kt0 + 1 < nk) step(kt0 + 1, std::integral_constant<int, 1>{});
-        if (kt0 + 2 < nk) step(kt0 + 2, std::integral_constant<int, 2>{});
-        if constexpr (NS > 3) if (kt0 + 3 < nk) step(kt0 + 3, std::integral_constant<int, 3 % NS>{});
-        if constexpr (NS > 4) if (kt0 + 4 < nk) step(kt0 + 4, std::integral_constant<int, 4 % NS>{});
+      auto kloop = [&](auto npa_c) {
+        for (int kt0 = 0; kt0 < nk; kt0 += NS) {
+          step(kt0, std::integral_constant<int, 0>{}, npa_c);
+          if (kt0 + 1 < nk) step(kt0 + 1, std::integral_constant<int, 1>{}, npa_c);
+          if (kt0 + 2 < nk) step(kt0 + 2, std::integral_constant<int, 2>{}, npa_c);
+          if constexpr (NS > 3)
+            if (kt0 + 3 < nk) step(kt0 + 3, std::integral_constant<int, 3 % NS>{}, npa_c);
+          if constexpr (NS > 4)
+            if (kt0 + 4 < nk) step(kt0 + 4, std::integral_constant<int, 4 % NS>{}, npa_c);
+        }
+      };
+      if constexpr (CF::SKIP >= 1) {
+        // On edge tiles a wave whose region lies outside C does no products,
+        // and a wave cut by the P edge computes only its slabs that reach into
+        // C (16-wide granularity); the skipped sums only reach C elements
+        // that are never stored.
+        const int p_ext = SW ? N - n0 - wn0 : M - m0 - wm0;
+        const int q_ext = SW ? M - m0 - wm0 : N - n0 - wn0;
+        const int npa = (p_ext <= 0 || q_ext <= 0) ? 0 : min(CF::FP, (p_ext + 15) / 16);
+        using std::integral_constant;
+        constexpr int F = CF::FP;
+        if (npa >= F) kloop(integral_constant<int, F>{});
+        else if (npa == 0) kloop(integral_constant<int, 0>{});
+        else if (npa == 1) kloop(integral_constant<int, 1>{});
+        else if (npa == 2) kloop(integral_constant<int, (F > 2 ? 2 : F)>{});
+        else if (npa == 3) kloop(integral_constant<int, (F > 3 ? 3 : F)>{});
+        else kloop(integral_constant<int, F>{});
+      } else {
+        kloop(std::integral_constant<int, CF::FP>{});
       }
     }
   }
@@ -793,8 +823,7 @@ hipError_t launch_scale(double beta, double* const* C, int64_t ldc, int m, int n
 //   3. k_vb_finish: per-class exclusive prefix P_c[i] over instances;
 //   4. k_vb_map: when it fits in the workspace, a map tile -> instance;
 //   5. k_vb_exec (x3): a persistent grid per class; each workgroup pops tile
-//      numbers from its class's atomic counter until the queue is empty,
-//      fetching the next number while it computes the current tile.
+//      numbers from its class's atomic counters until the queue is empty.
 // ---------------------------------------------------------------------------
 #ifndef BG_CFGVB_L
 #define BG_CFGVB_L 128, 64, 16, 32, 32, true
@@ -814,12 +843,23 @@ using CfgVbM = Cfg<BG_CFGVB_M>;
 using CfgVbS = Cfg<BG_CFGVB_S>;
 constexpr int VB_NC = 3;
 constexpr int PLAN_BLOCK = 256;
-constexpr int VB_CTRL = VB_NC + VB_NC * 8;  // totals, then one queue head per (class, XCD)
+// Queue heads, one per (class, XCD), each on its own 4 KB line: every pop
+// is a device-scope atomic, performed at the memory side, and heads sharing
+// a line would serialise all pops of the device on one channel.
+#ifndef BG_VB_HEAD_STRIDE
+#define BG_VB_HEAD_STRIDE 512
+#endif
+constexpr int HEAD_STRIDE = BG_VB_HEAD_STRIDE;             // int64 elements
+constexpr int HEAD_BASE = HEAD_STRIDE > VB_NC ? HEAD_STRIDE : VB_NC;
+constexpr int VB_CTRL = HEAD_BASE + VB_NC * 8 * HEAD_STRIDE;  // totals, then the heads
+__device__ __forceinline__ int64_t* vb_head(int64_t* ctrl, int cls, int x) {
+  return ctrl + HEAD_BASE + (int64_t)(cls * 8 + x) * HEAD_STRIDE;
+}
 
 struct VbLayout {
   int64_t* prefix;   // [VB_NC][batch + 1]
   int64_t* bsum;     // [VB_NC][nblocks]
-  int64_t* ctrl;     // [0..2] tiles per class, then queue heads [class][xcd]
+  int64_t* ctrl;     // [0..2] tiles per class, then the queue heads (vb_head)
   int* map;          // [map_cap]
   int64_t map_cap;
 };
@@ -943,7 +983,7 @@ __global__ __launch_bounds__(1024) void k_vb_blocks(int64_t* __restrict__ bsum, 
       __syncthreads();
     }
     if (threadIdx.x == 0) ctrl[c] = carry;                          // tiles of class c
-    if (threadIdx.x < 8) ctrl[VB_NC + c * 8 + threadIdx.x] = 0;     // its per-XCD heads
+    if (threadIdx.x < 8) *vb_head(ctrl, c, threadIdx.x) = 0;        // its per-XCD heads
     __syncthreads();
   }
 }
@@ -1007,19 +1047,21 @@ __global__ __launch_bounds__(CF::NT) void k_vb_exec(
   __shared__ int64_t s_q;
   const int64_t* prefix = prefix_all + (int64_t)cls * (batch + 1);
   const int64_t total = ctrl[cls];
+  if (total == 0) return;   // no tile of this class (uniform across the workgroup)
   int64_t all = 0, moff = 0;
   for (int c = 0; c < VB_NC; ++c) {
     all += ctrl[c];
     if (c < cls) moff += ctrl[c];
   }
   const bool use_map = all <= map_cap;
-  unsigned long long* heads = (unsigned long long*)&ctrl[VB_NC + cls * 8];
+
   const int home = blockIdx.x % NUM_XCD;
   for (int step = 0; step < NUM_XCD; ++step) {
     const int x = (home + step) % NUM_XCD;
     const int64_t lo = total * x / NUM_XCD, hi = total * (x + 1) / NUM_XCD;
     for (;;) {
-      if (threadIdx.x == 0) s_q = lo + (int64_t)atomicAdd(&heads[x], 1ull);
+      if (threadIdx.x == 0)
+        s_q = lo + (int64_t)atomicAdd((unsigned long long*)vb_head(ctrl, cls, x), 1ull);
       __syncthreads();
       const int64_t q = s_q;
       __syncthreads();

@@ -39,39 +39,37 @@ CANDIDATES = {
     ]),
     "BG_CFG128": ("u256+s512", [
         "128,64,16,16,64,true,2,false,0,3",
+        "128,64,16,16,64,true,2,false,1,3",
         "128,64,16,16,64,true,2,true,0,3",
         "128,64,16,16,64,true",
-        "128,64,16,16,64,true,2,true",
         "128,64,32,16,64,true,2,false,0,3",
-        "128,64,32,16,64,true,2,true,0,3",
         "64,64,16,16,64,true,2,false,0,3",
     ]),
     "BG_CFGVB_L": ("vb", [
-        "128,64,16,32,32,true",
-        "128,64,16,16,64,true",
-        "128,64,16,16,64,true,2,false,0,3",
-        "128,64,16,32,32,true,2,true",
-        "64,128,16,32,32,true",
-        "128,64,16,32,32,true,2,false,0,3",
         "128,64,16,16,64,true,2,false,1",
-        "128,64,16,16,64,true,2,false,2",
-        "128,64,32,16,64,true",
-        "128,64,16,16,64,true,1",
+        "128,64,16,16,64,true",
+        "128,64,16,32,32,true",
+        "128,64,16,16,64,true,2,false,1,3",
+        "128,64,16,32,32,true,2,false,1,3",
+        "64,64,16,16,64,true,2,false,1,3",
+        "64,64,16,16,32,true,2,false,1,3",
+        "128,64,32,16,64,true,2,false,1,3",
     ]),
     "BG_CFGVB_M": ("vb", [
+        "64,64,16,32,32,true",
+        "64,64,16,32,32,true,2,false,1",
+        "64,64,16,32,32,true,2,false,1,3",
+        "64,64,16,16,64,true,2,false,1,3",
         "64,64,16,32,32,true,2,true",
         "64,64,32,32,32,true,2,true",
-        "64,64,16,32,32,true",
-        "64,64,16,64,16,false,2,true",
-        "64,64,16,32,32,true,2,true,0,3",
     ]),
     "BG_CFGVB_S": ("vb", [
-        "32,32,16,32,32,false,2,true",
-        "32,32,16,32,32,true,2,true",
+        "32,32,16,32,32,false,1",
+        "32,32,16,32,32,true,1",
         "32,32,16,32,32,false",
-        "32,32,16,16,32,false,2,true",
+        "32,32,16,32,32,false,2,true",
+        "32,32,16,16,32,false,1,false,1",
         "32,32,16,32,32,false,2,true,0,3",
-        "32,32,16,32,32,true,2,true,0,4",
     ]),
 }
 
