@@ -170,6 +170,23 @@ __global__ __launch_bounds__(256) void k_mfma4_peak(double* sink, int iters, dou
   if (s == 1234.5678) sink[threadIdx.x] = s;
 }
 
+// int8 matrix core, v_mfma_i32_16x16x64_i8 (32768 operations per
+// instruction), 8 independent accumulator chains.
+__global__ __launch_bounds__(256) void k_i8_peak(int* sink, int iters, int seed) {
+  const int x = seed + (int)threadIdx.x;
+  const i4 a = {x, x ^ 0x01010101, x + 7, x * 3};
+  const i4 b = {x * 5, x ^ 0x10101010, x - 3, x + 11};
+  i4 acc[8];
+  for (int c = 0; c < 8; ++c) acc[c] = i4{c, 0, 0, 0};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[c], 0, 0, 0);
+  }
+  int s = 0;
+  for (int c = 0; c < 8; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  if (s == 0x12345678) sink[threadIdx.x] = s;
+}
+
 static float time_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   hipEventElapsedTime(&ms, a, b);
@@ -220,6 +237,24 @@ double mb_fp64_peak_ms(int kind, int grid, int iters, int reps, double* sink) {
   launch();
   hipEventRecord(e0, 0);
   for (int r = 0; r < reps; ++r) launch();
+  hipEventRecord(e1, 0);
+  hipError_t err = hipEventSynchronize(e1);
+  double ms = err == hipSuccess ? (double)time_ms(e0, e1) : -1.0;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return ms;
+}
+
+// Elapsed milliseconds of `reps` launches of the int8 matrix-core kernel
+// (grid workgroups of 256 threads, `iters` rounds), after one warm-up launch.
+double mb_i8_peak_ms(int grid, int iters, int reps, int* sink) {
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  hipLaunchKernelGGL(k_i8_peak, dim3(grid), dim3(256), 0, 0, sink, iters, 3);
+  hipEventRecord(e0, 0);
+  for (int r = 0; r < reps; ++r)
+    hipLaunchKernelGGL(k_i8_peak, dim3(grid), dim3(256), 0, 0, sink, iters, 3);
   hipEventRecord(e1, 0);
   hipError_t err = hipEventSynchronize(e1);
   double ms = err == hipSuccess ? (double)time_ms(e0, e1) : -1.0;

@@ -35,6 +35,8 @@ def lib():
         L.mb_mfma_f64_4x4x4.argtypes = [vp, vp, vp, vp]
         L.mb_fp64_peak_ms.restype = ctypes.c_double
         L.mb_fp64_peak_ms.argtypes = [ctypes.c_int] * 4 + [vp]
+        L.mb_i8_peak_ms.restype = ctypes.c_double
+        L.mb_i8_peak_ms.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
         L.mb_stream_ms.restype = ctypes.c_double
         L.mb_stream_ms.argtypes = [ctypes.c_int, vp, vp, ctypes.c_longlong, ctypes.c_int,
                                    ctypes.c_int, vp]
@@ -124,6 +126,17 @@ def fp64_peak_tflops(kind: str, grid: int | None = None, iters: int = 4000, reps
     return flop * reps / (ms * 1e-3) / 1e12, ms
 
 
+def int8_peak_tops(grid: int | None = None, iters: int = 2000, reps: int = 5):
+    """int8 matrix-core throughput (v_mfma_i32_16x16x64_i8, 8 chains) in
+    TOP/s."""
+    props = torch.cuda.get_device_properties(0)
+    grid = grid or props.multi_processor_count * 8
+    sink = torch.zeros(256, dtype=torch.int32, device="cuda")
+    ms = lib().mb_i8_peak_ms(grid, iters, reps, sink.data_ptr())
+    ops = grid * 4 * iters * 8 * 32768.0 * reps
+    return ops / (ms * 1e-3) / 1e12, ms
+
+
 STREAM_KINDS = {"copy_stride": 0, "read_stride": 1, "copy": 2, "read": 3, "copy_nt": 4,
                 "read_nt": 5}
 
@@ -154,6 +167,7 @@ def summary():
            "cus": torch.cuda.get_device_properties(0).multi_processor_count}
     for k in ("mfma", "mfma8", "mfma4x4", "valu"):
         out["fp64_%s_tflops" % k] = round(fp64_peak_tflops(k)[0], 2)
+    out["int8_mfma_tops"] = round(int8_peak_tops()[0], 1)
     for k in STREAM_KINDS:
         out["hbm_%s_gbps" % k] = round(stream_gbps(k)[0], 1)
     return out
