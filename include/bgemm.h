@@ -27,8 +27,10 @@
  * pointer per instance), the per-instance size arrays of the variable-size
  * call and d_info are DEVICE memory owned by the caller; the library never
  * frees or retains them.  alpha and beta are host values.  The handle owns
- * only its workspace, allocated by bg_create / bg_set_workspace; no compute
- * entry point allocates.
+ * only its workspace, allocated by bg_create / bg_set_workspace (the
+ * variable-size planner's buffers; in builds with the persistent uniform form
+ * its first 32 KiB also hold that form's tile queues); no compute entry point
+ * allocates.
  *
  * Semantics of the scalars (reference BLAS; the paper is silent):
  *   beta == 0            C is not read (NaN in C does not propagate);

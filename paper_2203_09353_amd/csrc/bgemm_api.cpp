@@ -229,6 +229,9 @@ bg_status_t bg_dgemm_batched(bg_handle_t h, char transa, char transb, int m, int
     a.alpha = alpha; a.beta = beta;
     a.A = dA; a.lda = lda; a.B = dB; a.ldb = ldb; a.C = dC; a.ldc = ldc;
     a.batch = batch;
+    a.num_cus = h->num_cus;
+    a.ws = h->ws;
+    a.ws_bytes = h->ws_bytes;
     const bg::TileClass cls = bg::pick_uniform_class(m, n, k, batch, h->num_cus, h->force_class);
     e = bg::launch_uniform(a, cls, h->stream);
     if (e == hipErrorInvalidValue) return BG_STATUS_NOT_SUPPORTED;

@@ -33,6 +33,9 @@ struct UniformArgs {
   const double* const* B; int64_t ldb;
   double* const* C; int64_t ldc;
   int batch;
+  int num_cus = 0;   // compute units of the device (sizes persistent grids)
+  void* ws = nullptr;         // handle workspace (queue heads of the persistent form)
+  size_t ws_bytes = 0;
 };
 
 // Launches the uniform batched GEMM (product path; alpha != 0, k > 0).

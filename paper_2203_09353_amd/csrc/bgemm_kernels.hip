@@ -735,6 +735,54 @@ __global__ __launch_bounds__(CF::NT) void k_uniform(
                         tn, (lptr)lds);
 }
 
+// Persistent form for the pipelined class (1; off by default): one grid of
+// resident workgroups that pop tiles from eight atomic queues, one per XCD
+// range (as the variable-size executor does), each head on its own 4 KiB
+// line of the handle's workspace, for batches with at least four k-steps per
+// tile and four tiles per resident workgroup.  Measured 1 % faster than one
+// workgroup per tile on 20,000 x 256^3, equal on 512^3 and up to 30 % faster
+// on odd shapes (129 x 513 x 257), but it read 14 % (256^3) and 55 % (512^3)
+// more from HBM than the algorithmic bytes, which one workgroup per tile
+// matches exactly; a static deal of the tiles was slower.
+#ifndef BG_UNIFORM_PERSIST
+#define BG_UNIFORM_PERSIST 0
+#endif
+constexpr int UQ_STRIDE = 512;                   // int64 elements between heads
+constexpr size_t UQ_BYTES = (size_t)NUM_XCD * UQ_STRIDE * 8;
+// The persistent form is used when every workgroup gets this many tiles.
+constexpr int64_t UQ_MIN_TILES_PER_WG = 4;
+
+__global__ void k_uq_reset(unsigned long long* heads) {
+  if (threadIdx.x < NUM_XCD) heads[threadIdx.x * UQ_STRIDE] = 0;
+}
+
+template <class CF, bool TA, bool TB>
+__global__ __launch_bounds__(CF::NT) void k_uniform_persist(
+    int M, int N, int K, double alpha, const double* const* __restrict__ Ap, int64_t lda,
+    const double* const* __restrict__ Bp, int64_t ldb, double beta,
+    double* const* __restrict__ Cp, int64_t ldc, int tiles_m, int tiles_per_inst,
+    int64_t total_tiles, unsigned long long* __restrict__ heads) {
+  __shared__ double lds[TileSmem<CF, TA, TB>::TOTAL];
+  __shared__ int64_t s_q;
+  const int home = blockIdx.x % NUM_XCD;
+  for (int step = 0; step < NUM_XCD; ++step) {
+    const int x = (home + step) % NUM_XCD;
+    const int64_t lo = total_tiles * x / NUM_XCD, hi = total_tiles * (x + 1) / NUM_XCD;
+    for (;;) {
+      if (threadIdx.x == 0) s_q = lo + (int64_t)atomicAdd(&heads[x * UQ_STRIDE], 1ull);
+      __syncthreads();
+      const int64_t id = s_q;
+      __syncthreads();
+      if (id >= hi) break;
+      const int64_t inst = id / tiles_per_inst;
+      const int t = (int)(id - inst * tiles_per_inst);
+      gemm_tile<CF, TA, TB>(Ap[inst], lda, Bp[inst], ldb, Cp[inst], ldc, M, N, K, alpha, beta,
+                            t % tiles_m, t / tiles_m, (lptr)lds);
+      __syncthreads();  // LDS free for the next tile
+    }
+  }
+}
+
 template <class CF, bool TA, bool TB>
 static hipError_t launch_uniform_t(const UniformArgs& a, hipStream_t s) {
   const int tiles_m = (a.m + CF::BM - 1) / CF::BM;
@@ -742,6 +790,22 @@ static hipError_t launch_uniform_t(const UniformArgs& a, hipStream_t s) {
   const int64_t tpi = (int64_t)tiles_m * tiles_n;
   const int64_t total = tpi * a.batch;
   if (tpi > INT32_MAX) return hipErrorInvalidValue;
+  if (BG_UNIFORM_PERSIST && CF::PIPE >= 3 && a.num_cus > 0 && a.ws && a.ws_bytes >= UQ_BYTES) {
+    auto kern = k_uniform_persist<CF, TA, TB>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, CF::NT, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    const int64_t grid = (int64_t)a.num_cus * per_cu;
+    if (total >= UQ_MIN_TILES_PER_WG * grid && a.k >= 4 * CF::BK) {
+      unsigned long long* heads = (unsigned long long*)a.ws;
+      hipLaunchKernelGGL(k_uq_reset, dim3(1), dim3(64), 0, s, heads);
+      hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(CF::NT), 0, s, a.m, a.n, a.k, a.alpha,
+                         a.A, a.lda, a.B, a.ldb, a.beta, a.C, a.ldc, tiles_m, (int)tpi, total,
+                         heads);
+      return hipGetLastError();
+    }
+  }
   const int64_t per_xcd = (total + NUM_XCD - 1) / NUM_XCD;
   const int64_t grid = per_xcd * NUM_XCD;
   if (grid > INT32_MAX) return hipErrorInvalidValue;
