@@ -6,6 +6,7 @@
     python bench.py --workload gram15|gram21 [--steps K]
     python bench.py --workload gate21 [--steps K]
     python bench.py --workload config1|vb8 [--cold]
+    python bench.py --workload ksweep [--steps K]
 
 A step is one pass over every part of the workload: the three uniform
 batches of 64^3, 256^3 and 512^3 (symmetric) instances through
@@ -45,6 +46,11 @@ otherwise stay cache-resident between launches.
 ``--workload gate21`` times the two-spin gate on 64 states of S = 21 spins
 (2^21 binary64 complex amplitudes each, 32 MiB), a new seeded site and gate
 per state; HBM-bound (each state read and written once per step).
+
+``--workload ksweep`` is a diagnostic of the uniform path: batches of 256^2
+and 512^2 C blocks at one fixed flop count, k from 32 to 4096, beta 0 and 1;
+at fixed flops the number of tiles falls as k grows, which separates each
+tile's fixed cost from the rate of the k loop.
 """
 from __future__ import annotations
 
@@ -606,6 +612,53 @@ def gate_bench(args, h):
     print(json.dumps(out), flush=True)
 
 
+def ksweep_bench(args, h):
+    """The ksweep line: uniform 'N','N' batches of 256^2 and 512^2 C blocks
+    at a fixed 6.7e11 flop (20,000 x 256^3 x 2), k from 32 to 4096, with
+    beta 0 and 1.  At fixed flops the tile count falls as k grows, so the
+    rate against k separates the per-tile cost (pipeline fill, epilogue,
+    the C read with beta != 0) from the k-loop's own rate."""
+    import torch
+    from paper_2203_09353_amd import workloads
+    rows = []
+    worst = 0.0
+    for (m, n) in ((256, 256), (512, 512)):
+        for k in (32, 64, 128, 256, 512, 1024, 2048, 4096):
+            batch = max(1, int(20000 * 256 ** 3 / (m * n * k)))
+            row = {"m": m, "n": n, "k": k, "batch": batch}
+            for beta in (0.0, 1.0):
+                p = workloads.uniform_part("k%d" % k, batch, m, n, k, 1.0, beta, 12)
+                if args.check > 0:
+                    worst = max(worst, sampled_parity(h, [p], 1)[p.name])
+                for _ in range(max(1, args.warmup)):
+                    part_launch(h, p)
+                stream = torch.cuda.current_stream()
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(args.steps)]
+                torch.cuda.synchronize()
+                for e0, e1 in ev:
+                    e0.record(stream)
+                    part_launch(h, p)
+                    e1.record(stream)
+                torch.cuda.synchronize()
+                ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+                key = "beta%d" % int(beta)
+                row[key + "_ms"] = round(ms, 4)
+                row[key + "_tflops"] = round(p.flops / (ms * 1e-3) / 1e12, 2)
+                del p
+                torch.cuda.empty_cache()
+            rows.append(row)
+            log(json.dumps(row))
+    best = max(max(r["beta0_tflops"], r["beta1_tflops"]) for r in rows)
+    out = {"metric": "uniform FP64 batched GEMM TFLOP/s against k at fixed flops",
+           "value": best, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded uniform[-1,1))",
+           "config": {"workload": "ksweep", "flops_per_batch": 2 * 20000 * 256 ** 3},
+           "rows": rows, "parity_max_rel_fro": worst}
+    print(json.dumps(out), flush=True)
+
+
 def sampled_parity(h, parts, per_part, seed=11):
     """Runs one step and compares `per_part` seeded instances of every part
     with the CPU oracle (inputs copied to the host before the call)."""
@@ -761,6 +814,9 @@ def main():
         return
     if args.workload == "gate21":
         gate_bench(args, h)
+        return
+    if args.workload == "ksweep":
+        ksweep_bench(args, h)
         return
     log("building workload %s" % args.workload)
     t0 = time.perf_counter()
