@@ -109,6 +109,17 @@ struct Cfg {
 #ifndef BG_PIPE_ANY_LD
 #define BG_PIPE_ANY_LD 1
 #endif
+// Pipelined path: a k-step's refill loads issued after its first 16-slice's
+// second fragment read (1: their address arithmetic overlaps the LDS reads
+// and the first products), or right after the barrier (0).
+#ifndef BG_PIPE_LATE_REFILL
+#define BG_PIPE_LATE_REFILL 1
+#endif
+// Pipelined path: wave priority raised from a k-step's barrier to its end
+// (1), or left at 0.
+#ifndef BG_PIPE_SETPRIO
+#define BG_PIPE_SETPRIO 1
+#endif
 // Epilogue C loads all issued before the stores (1), or per element (0).
 #ifndef BG_EPI_BATCH
 #define BG_EPI_BATCH 1
@@ -522,7 +533,16 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
         else __builtin_amdgcn_s_waitcnt(waitcnt_imm(3 * PS::DPT, 0));
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        if (kt + NS - 1 < nk) issue(kt + NS - 1, (st + NS - 1) % NS);
+        // Wave priority raised from the barrier to the end of the step, and
+        // the refill loads issued after the second fragment read: together
+        // measured 1.4-4.5 % faster on 256^3, 512^3 and mixed-size batches.
+        if constexpr (BG_PIPE_SETPRIO) __builtin_amdgcn_s_setprio(1);
+        auto refill = [&]() {
+          asm volatile("" ::: "memory");
+          if (kt + NS - 1 < nk) issue(kt + NS - 1, (st + NS - 1) % NS);
+          asm volatile("" ::: "memory");
+        };
+        if constexpr (NPA == 0 || !BG_PIPE_LATE_REFILL) refill();
         const lcptr la = lds + st * PS::STAGE, lb = la + TAs::ELEMS;
         const lcptr lp = SW ? lb : la;
         const lcptr lq = SW ? la : lb;
@@ -540,6 +560,8 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
                 read_p_sw<TAs, NPA, TA>(lp, p0, kk, tp, lane, fp);
                 read_q_sw<TBs, CF::GQ, !TB>(lq, q0, kk, tp, lane, fq);
               }
+              if constexpr (BG_PIPE_LATE_REFILL)
+                if (kk == 0 && tp == 1) refill();
 #pragma unroll
               for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -551,6 +573,7 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
             }
           }
         }
+        if constexpr (BG_PIPE_SETPRIO) __builtin_amdgcn_s_setprio(0);
       };
       auto kloop = [&](auto npa_c) {
         for (int kt0 = 0; kt0 < nk; kt0 += NS) {
