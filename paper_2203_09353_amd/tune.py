@@ -28,7 +28,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tune_cache.json")
 ARCH = os.environ.get("BG_OFFLOAD_ARCH", "gfx950")
 
-# class macro -> (workload parts timed, candidate shapes)
+# class macro -> (workload parts timed, candidate shapes).  Each list is in
+# order of preference: a shape within TIE of the fastest wins over it when it
+# comes earlier (so timing noise does not trade away, say, edge skipping,
+# which leaves the tuning workloads' times unchanged but speeds up odd extents).
+TIE = 0.003
 CANDIDATES = {
     "BG_CFG64": ("u64", [
         "64,64,16,32,32,true,2,true",
@@ -38,8 +42,8 @@ CANDIDATES = {
         "64,64,16,32,32,true,2,false",
     ]),
     "BG_CFG128": ("u256+s512", [
-        "128,64,16,16,64,true,2,false,0,3",
         "128,64,16,16,64,true,2,false,1,3",
+        "128,64,16,16,64,true,2,false,0,3",
         "128,64,16,16,64,true,2,true,0,3",
         "128,64,16,16,64,true",
         "128,64,32,16,64,true,2,false,0,3",
@@ -72,6 +76,12 @@ CANDIDATES = {
         "32,32,16,32,32,false,2,true,0,3",
     ]),
 }
+
+
+def pick(times: dict, order: list) -> str:
+    """The earliest shape of `order` whose time is within TIE of the best."""
+    best = min(times.values())
+    return next(c for c in order if c in times and times[c] <= best * (1.0 + TIE))
 
 
 def load_cache() -> dict:
@@ -164,7 +174,7 @@ def cmd_run(out: str):
                 times[shape] = ms
                 print(json.dumps({"class": macro, "shape": shape, "workload": wl, "ms": round(ms, 4)}),
                       flush=True)
-            best = min(times, key=times.get)
+            best = pick(times, cands)
             entry[macro] = {"shape": best, "workload": wl, "ms": round(times[best], 4),
                             "candidates": {c: round(t, 4) for c, t in times.items()}}
         del parts

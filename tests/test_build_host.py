@@ -27,3 +27,12 @@ def test_other_kernels_and_clean_builds_pass():
 def test_build_asks_the_compiler_for_resource_remarks():
     assert "-Rpass-analysis=kernel-resource-usage" in build.RESOURCE_REMARKS
     assert set(build.COUNTED_WAIT_KERNELS) == {"k_uniform", "k_vb_exec"}
+
+
+def test_tuner_prefers_the_earlier_shape_on_a_tie():
+    from paper_2203_09353_amd import tune
+    order = ["a", "b", "c"]
+    assert tune.pick({"a": 10.02, "b": 10.0, "c": 11.0}, order) == "a"     # within TIE
+    assert tune.pick({"a": 10.5, "b": 10.0, "c": 11.0}, order) == "b"      # a clearly slower
+    assert tune.pick({"b": 10.0, "c": 9.0}, order) == "c"                  # a not built
+    assert tune.pick({"c": 9.0}, order) == "c"
