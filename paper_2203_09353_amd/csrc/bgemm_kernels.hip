@@ -741,8 +741,22 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
 // ---------------------------------------------------------------------------
 constexpr int NUM_XCD = 8;
 
+// Waves per SIMD a tile kernel is compiled for (its register budget).  The
+// 512-thread 'T','N' uniform kernel would take 132 VGPRs and run one
+// workgroup per CU; held to 4 waves (128 VGPRs, the two workgroups its LDS
+// allows) it still compiles without a spill, which the build checks, and
+// runs 8 % faster.  The others fit 128 already ('N','N', 'T','T') or would
+// spill ('N','T' and the variable-size 'T','N').
+#ifndef BG_TN_WAVES
+#define BG_TN_WAVES 4
+#endif
 template <class CF, bool TA, bool TB>
-__global__ __launch_bounds__(CF::NT) void k_uniform(
+constexpr int uniform_min_waves() {
+  return (CF::NT >= 512 && TA && !TB) ? BG_TN_WAVES : 1;
+}
+
+template <class CF, bool TA, bool TB>
+__global__ __launch_bounds__(CF::NT, (uniform_min_waves<CF, TA, TB>())) void k_uniform(
     int M, int N, int K, double alpha, const double* const* __restrict__ Ap, int64_t lda,
     const double* const* __restrict__ Bp, int64_t ldb, double beta,
     double* const* __restrict__ Cp, int64_t ldc, int tiles_m, int tiles_per_inst,
@@ -780,7 +794,7 @@ __global__ void k_uq_reset(unsigned long long* heads) {
 }
 
 template <class CF, bool TA, bool TB>
-__global__ __launch_bounds__(CF::NT) void k_uniform_persist(
+__global__ __launch_bounds__(CF::NT, (uniform_min_waves<CF, TA, TB>())) void k_uniform_persist(
     int M, int N, int K, double alpha, const double* const* __restrict__ Ap, int64_t lda,
     const double* const* __restrict__ Bp, int64_t ldb, double beta,
     double* const* __restrict__ Cp, int64_t ldc, int tiles_m, int tiles_per_inst,
