@@ -726,6 +726,49 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
       }
       __syncthreads();
     }
+#ifndef BG_EPI_LDS_REG
+#define BG_EPI_LDS_REG 1
+#endif
+    // Interior tiles of the classes without the pipelined path take an LDS
+    // epilogue too (the loop's last barrier has freed the stages):
+    // consecutive lanes handle consecutive 16-byte row pairs of one column
+    // of C.
+    constexpr int RS = CF::BM + 4;
+    constexpr int RPAIRS = CF::BN * CF::BM / 2;
+    if constexpr (BG_EPI_LDS_REG && CF::PIPE == 0 && !CF::CPRE && RPAIRS % CF::NT == 0 &&
+                  CF::BN * RS <= TileSmem<CF, TA, TB>::TOTAL) {
+      if (m0 + CF::BM <= M && n0 + CF::BN <= N) {
+        constexpr int RPT = RPAIRS / CF::NT;
+        d2 cw[RPT];
+        if (beta != 0.0) {
+#pragma unroll
+          for (int it = 0; it < RPT; ++it) {
+            const int u = it * CF::NT + tid, col = u / (CF::BM / 2), pr = u % (CF::BM / 2);
+            cw[it] = *(const AS_GLOBAL d2u*)(C + m0 + 2 * pr + (int64_t)(n0 + col) * ldc);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < CF::FP; ++i)
+#pragma unroll
+          for (int j = 0; j < CF::GQ; ++j)
+            lds[(c_col(i, j) - n0) * RS + (c_row(i, j) - m0)] = acc[i][j];
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < RPT; ++it) {
+          const int u = it * CF::NT + tid, col = u / (CF::BM / 2), pr = u % (CF::BM / 2);
+          const d2 a = *(const AS_LDS d2*)(lds + col * RS + 2 * pr);
+          d2 y;
+          y.x = alpha * a.x;
+          y.y = alpha * a.y;
+          if (beta != 0.0) {
+            y.x = y.x + beta * cw[it].x;
+            y.y = y.y + beta * cw[it].y;
+          }
+          *(AS_GLOBAL d2u*)(C + m0 + 2 * pr + (int64_t)(n0 + col) * ldc) = y;
+        }
+        return;
+      }
+    }
   }
 
   // Epilogue.  All C loads (beta != 0) are issued first, from clamped
