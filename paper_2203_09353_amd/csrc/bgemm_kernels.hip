@@ -615,9 +615,24 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
         // element as the epilogue below, so the results are bit-identical;
         // measured 2.3 % faster on the variable-size batch and up to 19 % on
         // short-k uniform batches (512 x 512 x 16).
-        constexpr int S = CF::BM + 4;                  // column stride in LDS
+#ifndef BG_EPI_XOR
+#define BG_EPI_XOR 1
+#endif
+        // Column stride in LDS; with BG_EPI_XOR the columns are unpadded and
+        // each column's 16-byte row pairs are XOR-swizzled by column, so the
+        // products' writes (16 columns x 4 rows per instruction) hit distinct
+        // banks in each half-wave, and the read-back of one column stays a
+        // permutation of it (variable-size batch 0.9 % faster than padding
+        // the columns by 4).
+        constexpr int S = BG_EPI_XOR ? CF::BM : CF::BM + 4;
         constexpr int CPW = CF::BN / (CF::NT / 64);    // columns per wave
         static_assert(CF::BN * S <= PS::TOTAL, "C tile must fit the stages");
+        auto epi_off = [](int c, int r) {  // LDS offset of tile element (row r, column c)
+          if constexpr (BG_EPI_XOR)
+            return c * S + 2 * ((r >> 1) ^ ((((c >> 2) + 4 * (c & 1)) & 7) << 1)) + (r & 1);
+          else
+            return c * S + r;
+        };
         if (m0 + CF::BM <= M && n0 + CF::BN <= N && !CP) {
           const int wv = tid >> 6, ln = tid & 63;
           d2 cw[CPW];
@@ -631,12 +646,12 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
           for (int i = 0; i < CF::FP; ++i)
 #pragma unroll
             for (int j = 0; j < CF::GQ; ++j)
-              lds[(c_col(i, j) - n0) * S + (c_row(i, j) - m0)] = acc[i][j];
+              lds[epi_off(c_col(i, j) - n0, c_row(i, j) - m0)] = acc[i][j];
           __syncthreads();
 #pragma unroll
           for (int i = 0; i < CPW; ++i) {
             const int cl = wv * CPW + i;
-            const d2 a = *(const AS_LDS d2*)(lds + cl * S + 2 * ln);
+            const d2 a = *(const AS_LDS d2*)(lds + epi_off(cl, 2 * ln));
             d2 y;
             y.x = alpha * a.x;
             y.y = alpha * a.y;
@@ -678,13 +693,13 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
           for (int i = 0; i < CF::FP; ++i)
 #pragma unroll
             for (int j = 0; j < CF::GQ; ++j)
-              lds[(c_col(i, j) - n0) * S + (c_row(i, j) - m0)] = acc[i][j];
+              lds[epi_off(c_col(i, j) - n0, c_row(i, j) - m0)] = acc[i][j];
           __syncthreads();
 #pragma unroll
           for (int i = 0; i < CPW; ++i) {
             const int cl = wv * CPW + i, col = n0 + cl;
             if (col < N && one) {
-              const d2 a = *(const AS_LDS d2*)(lds + cl * S + 2 * ln);
+              const d2 a = *(const AS_LDS d2*)(lds + epi_off(cl, 2 * ln));
               d2 y;
               y.x = alpha * a.x;
               y.y = alpha * a.y;
