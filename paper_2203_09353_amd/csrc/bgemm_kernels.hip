@@ -54,6 +54,28 @@ typedef AS_GLOBAL double* gptr;
 typedef AS_LDS double* lptr;
 typedef const AS_LDS double* lcptr;
 
+// Accesses to C on interior tiles.  A tile reads its part of C once and
+// writes it once, so these are nontemporal: the 200,000 x 64^3 batch (half of
+// its bytes are C reads and writes) runs 2.5-3.5 % faster, 256^3 0.1-0.7 %,
+// the variable-size batch within noise.  Edge tiles keep ordinary accesses
+// (nontemporal there made the variable-size batch 0.5 % slower), and so do
+// the operand loads (nontemporal A and B loads were faster still on 64^3 but
+// made the variable-size batch 7 % slower: its tiles share A and B panels
+// through the caches).
+#ifndef BG_NT_C
+#define BG_NT_C 1
+#endif
+template <class T>
+__device__ __forceinline__ T ld_c(const AS_GLOBAL T* p) {
+  if constexpr (BG_NT_C) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <class T>
+__device__ __forceinline__ void st_c(AS_GLOBAL T* p, T v) {
+  if constexpr (BG_NT_C) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // ---------------------------------------------------------------------------
 // Tile configurations: C tile BM x BN per workgroup, BK of k per LDS stage,
 // wave tile WM x WN, SWAP selects the C^T form (P = op(B)^T, Q = op(A)).
@@ -639,7 +661,7 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
           if (beta != 0.0) {
 #pragma unroll
             for (int i = 0; i < CPW; ++i)
-              cw[i] = *(const AS_GLOBAL d2u*)(C + m0 + 2 * ln + (int64_t)(n0 + wv * CPW + i) * ldc);
+              cw[i] = ld_c((const AS_GLOBAL d2u*)(C + m0 + 2 * ln + (int64_t)(n0 + wv * CPW + i) * ldc));
           }
           __syncthreads();  // every wave is done reading the last stage
 #pragma unroll
@@ -659,7 +681,7 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
               y.x = y.x + beta * cw[i].x;
               y.y = y.y + beta * cw[i].y;
             }
-            *(AS_GLOBAL d2u*)(C + m0 + 2 * ln + (int64_t)(n0 + cl) * ldc) = y;
+            st_c((AS_GLOBAL d2u*)(C + m0 + 2 * ln + (int64_t)(n0 + cl) * ldc), (d2u)y);
           }
           return;
         }
@@ -809,7 +831,7 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
 #pragma unroll
           for (int it = 0; it < RPT; ++it) {
             const int u = it * CF::NT + tid, col = u / (CF::BM / 2), pr = u % (CF::BM / 2);
-            cw[it] = *(const AS_GLOBAL d2u*)(C + m0 + 2 * pr + (int64_t)(n0 + col) * ldc);
+            cw[it] = ld_c((const AS_GLOBAL d2u*)(C + m0 + 2 * pr + (int64_t)(n0 + col) * ldc));
           }
         }
 #pragma unroll
@@ -829,7 +851,7 @@ __device__ __forceinline__ void gemm_tile(const double* A_, int64_t lda, const d
             y.x = y.x + beta * cw[it].x;
             y.y = y.y + beta * cw[it].y;
           }
-          *(AS_GLOBAL d2u*)(C + m0 + 2 * pr + (int64_t)(n0 + col) * ldc) = y;
+          st_c((AS_GLOBAL d2u*)(C + m0 + 2 * pr + (int64_t)(n0 + col) * ldc), (d2u)y);
         }
         return;
       }
